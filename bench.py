@@ -1,0 +1,202 @@
+"""Throughput benchmark of the fused lattice Boltzmann update on one MI355X.
+
+Workload: the 4096 x 4096 porous cavity (FP32 storage and arithmetic, AA
+pattern), power-law n = 0.8, Da = 1e-2, Ra = 1e5, Pr = 10, eps = 0.6, from
+rest.  One step = one fused stream + collide of all nodes for both the D2Q9
+flow and D2Q5 thermal populations; the reductions (hot-wall Nusselt number
+and the max |dT| residual) run on device every 1000 steps, as in a
+run-to-steady loop.  W untimed warm-up steps, then K timed steps between two
+synchronisations.
+
+Metric: MLUPS (million node updates per second, flow + thermal).  Also
+reported: the roofline of the dominant (step) kernel from its HIP-event-timed
+launches against the 8 TB/s HBM peak, with 112 algorithmic bytes per node
+update (9 + 5 FP32 populations read once and written once), the measured
+ceiling of a plain streaming copy, and the FP64 CPU oracle timed on a bounded
+sample of the same workload on this host.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+N = 4096
+PHYS = dict(n=0.8, Da=1e-2, Ra=1e5, Pr=10.0, eps=0.6)
+BYTES_PER_NODE = 112  # 14 FP32 populations, each read once and written once
+HBM_PEAK_GBS = 8000.0
+CHECK_EVERY = 1000
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_fp32_4096_traffic.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_2011_15073_amd", "csrc", "pm_kernels.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash():
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def read_traffic():
+    """HBM bytes per step launch from the committed rocprofv3 counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or None
+    when absent or taken on a different kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if "=" in line and not line.lstrip().startswith("#"):
+            k, v = line.split("=", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(budget_s=15.0):
+    """The FP64 oracle on the same 4096^2 workload: one warm-up step, then as
+    many steps as fit in about budget_s seconds (at least one)."""
+    import oracle as O
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+    orc = O.Oracle.from_physics(O.physics(N, **PHYS))
+    t0 = time.perf_counter()
+    orc.step(1)
+    t1 = time.perf_counter()
+    per = t1 - t0
+    k = max(1, min(50, int(budget_s / max(per, 1e-3))))
+    t0 = time.perf_counter()
+    orc.step(k)
+    dt = time.perf_counter() - t0
+    del orc
+    return {"value": round(N * N * k / dt / 1e6, 3), "unit": "MLUPS", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{k} steps of the 4096x4096 workload after 1 warm-up step, FP64, "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--roofline-steps", type=int, default=400)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the path is measured on one GPU's share; see the sharding notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2011_15073_amd as P
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    log(f"bench: {N}x{N} fp32 {PHYS}, warmup {args.warmup}, steps {args.steps}")
+    cav = P.Cavity(N, dtype="fp32", device="cuda:0", **PHYS)
+    stream = cav.stream
+
+    # warm-up (also builds the step graphs)
+    cav.step(args.warmup)
+    cav.nu()
+    torch.cuda.synchronize()
+    log("bench: warm-up done")
+
+    # timed region: K steps with the on-device reductions every CHECK_EVERY steps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    left = args.steps
+    nus = []
+    while left > 0:
+        k = min(CHECK_EVERY, left)
+        cav.step(k)
+        left -= k
+        if k == CHECK_EVERY:
+            nus.append(cav.nu())
+            cav.residual()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = elapsed * 1e3 / args.steps
+    mlups = N * N * args.steps / elapsed / 1e6
+    log(f"bench: {mlups:.1f} MLUPS, {ms_per_step:.4f} ms/step, Nu {nus[-1] if nus else cav.nu():.6f}")
+
+    # roofline of the step kernel: back-to-back launches bracketed by HIP events
+    # on the context's stream
+    rs = args.roofline_steps - args.roofline_steps % 2
+    with torch.cuda.stream(stream):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        cav.step(rs)
+        e1.record(stream)
+    e1.synchronize()
+    avg_s = e0.elapsed_time(e1) / 1e3 / rs
+    achieved = BYTES_PER_NODE * N * N / avg_s / 1e9
+    log(f"bench: step kernel {avg_s * 1e6:.1f} us/launch, {achieved:.0f} GB/s")
+
+    # measured streaming-copy ceiling (read + write of 1 GiB)
+    nbytes = 1 << 30
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        P.copy_probe(src, dst, stream)
+    with torch.cuda.stream(stream):
+        c0 = torch.cuda.Event(enable_timing=True)
+        c1 = torch.cuda.Event(enable_timing=True)
+        c0.record(stream)
+        for _ in range(10):
+            P.copy_probe(src, dst, stream)
+        c1.record(stream)
+    c1.synchronize()
+    copy_gbs = 2 * nbytes * 10 / (c0.elapsed_time(c1) / 1e3) / 1e9
+    del src, dst
+    log(f"bench: copy ceiling {copy_gbs:.0f} GB/s")
+
+    traffic = read_traffic()
+    result = {
+        "metric": "MLUPS (flow+thermal)",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "porous power-law cavity 4096x4096, D2Q9 MRT + D2Q5 MRT, "
+                               "FP32 AA layout, n=0.8 Da=1e-2 Ra=1e5 Pr=10 eps=0.6, "
+                               "Nu + residual on device every 1000 steps",
+                   "nodes": N * N, "steps_timed": args.steps},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic,
+                     "kernel": "k_step (fused stream+collide, both parities)",
+                     "us_per_launch": round(avg_s * 1e6, 2),
+                     "algorithmic_bytes_per_launch": BYTES_PER_NODE * N * N,
+                     "copy_ceiling_GBps": round(copy_gbs, 1)},
+        "nu_bar": nus[-1] if nus else None,
+    }
+    if not args.no_cpu_baseline:
+        del cav
+        torch.cuda.empty_cache()
+        log("bench: timing the CPU oracle on a bounded sample ...")
+        result["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

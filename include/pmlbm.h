@@ -1,0 +1,179 @@
+/*
+ * pmlbm.h -- C ABI of the MI355X (gfx950) lattice Boltzmann library for
+ * natural convection of a power-law fluid in a porous square cavity
+ * (Islam, Nag & Molla, ICME 2019, arXiv:2011.15073).
+ *
+ * Method (equation numbers count the paper's displayed equations in order):
+ *   - D2Q9 MRT collision in moment space with forcing, Eq. (12), relaxation
+ *     rates Eq. (13), velocities Eq. (14), nu = c_s^2 (tau - 1/2) Eq. (15),
+ *     macroscopic rho and u Eqs. (16)-(17);
+ *   - Boussinesq buoyancy (Eq. 9's +Pr theta) and a Brinkman-Forchheimer
+ *     porous drag (Eq. 8's Darcy term -U D/Da, generalised with porosity and
+ *     the Forchheimer term);
+ *   - local modified power-law viscosity, Eq. (21), with the shear rate from
+ *     the non-equilibrium moments, Eqs. (22)-(23);
+ *   - D2Q5 MRT thermal update, Eqs. (18)-(20), hot left wall, cold right wall,
+ *     adiabatic top and bottom (the text of the "Mathematical Formulations"
+ *     section; Eq. (5) as printed swaps the walls);
+ *   - hot-wall average Nusselt number, Eq. (24), and the steady-state
+ *     residual max |T_k - T_{k-m}|.
+ *
+ * Lattice units: dx = dt = 1; node (i, j) at x = i + 1/2, y = j + 1/2; walls
+ * halfway between nodes, so the cavity side L equals the node count N.
+ * Parameter mapping (the paper gives none): U_lb = mach / sqrt(3);
+ * nu0_lb = Pr / sqrt(Ra)^(2-n) * U_lb * N; alpha_lb = U_lb * N / sqrt(Ra);
+ * g*beta_lb = Pr * U_lb^2 / N; K = Da * N^2; F_eps = 1.75 / sqrt(150 eps^3).
+ *
+ * Conventions for every call:
+ *   - Return value: PM_OK (0) or a negative PM_E* code; nothing aborts or
+ *     throws across the ABI.  pm_last_error(ctx) holds a message for the most
+ *     recent failure on that context (pm_last_error(NULL): the most recent
+ *     failure of a call that had no context yet).
+ *   - Device memory is always owned by the caller: the workspace passed to
+ *     pm_init, and every output buffer.  The library allocates only its host
+ *     context and (for pm_step) HIP graph objects, released by pm_destroy.
+ *   - A context is bound to the HIP stream given to pm_init; every call
+ *     enqueues on that stream.  Calls that return host values (pm_nu,
+ *     pm_residual, pm_run_to_steady) synchronise that stream.  A context is
+ *     not thread-safe.
+ *   - Grids are stored as planes [q][ny][nx], x fastest.
+ */
+#ifndef PMLBM_H
+#define PMLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PM_OK 0
+#define PM_EINVAL (-1)    /* invalid argument or parameters */
+#define PM_EDEVICE (-2)   /* HIP runtime error (message kept) */
+#define PM_EDIVERGED (-3) /* NaN/Inf met in a reduction */
+#define PM_ESTATE (-4)    /* buffer size or state mismatch */
+
+#define PM_FP32 0 /* FP32 storage and arithmetic; FP64 reductions */
+#define PM_FP64 1 /* FP64 storage and arithmetic */
+
+#define PM_CLAMP_NU 0    /* nu = clamp(nu0 gamma*^(n-1), nu_lo nu0, nu_hi nu0) */
+#define PM_CLAMP_GAMMA 1 /* nu = nu0 clamp(gamma*, nu_lo, nu_hi)^(n-1): the
+                            thresholds gamma1, gamma2 of Eq. (21) */
+
+typedef struct pm_ctx pm_ctx;
+
+/* Problem parameters.  Groups of Eq. (6) plus porosity, Mach number and the
+ * viscosity bounds.  Fill with pm_params_default() and override. */
+typedef struct {
+  int32_t nx, ny;                 /* nodes; nx = ny for the paper's cavity */
+  int32_t periodic_x, periodic_y; /* 1 = periodic axis instead of walls */
+  double n;        /* power-law index (> 0); 1 = Newtonian */
+  double Da;       /* Darcy number K/L^2 (> 0); +inf = clear fluid */
+  double Ra, Pr;   /* Rayleigh, Prandtl numbers (> 0) */
+  double eps;      /* porosity in (0, 1] */
+  double mach;     /* lattice Mach number (default 0.1) */
+  double nu_lo, nu_hi; /* clamp bounds, see PM_CLAMP_* (default 0.1, 10) */
+  int32_t clamp_mode;  /* PM_CLAMP_NU (default) or PM_CLAMP_GAMMA */
+  int32_t dtype;       /* PM_FP32 (default) or PM_FP64 */
+  int32_t forchheimer; /* 1 (default): Ergun F_eps; 0: Darcy-Brinkman only */
+  int32_t has_logda;   /* 1: per-cell log10(Da) plane from pm_set_logda */
+  double s_e, s_eps, s_q; /* D2Q9 rates s1, s2, s4 = s6 (default 1.4, 1.4, 1.2) */
+  double sT_e, sT_nu;     /* D2Q5 higher-moment rates (default 1.0, 1.0) */
+  double gx, gy;          /* extra uniform body force, lattice units (default 0) */
+  double T_init;          /* initial uniform theta (default 0.5) */
+} pm_params;
+
+/* Lattice values derived from pm_params (read-only description). */
+typedef struct {
+  double U_lb, nu0, nu_min, nu_max, gamma_scale;
+  double eps, K, Feps, gbeta, T_m, alpha;
+  double tau0, tau_min, tau_max, tau_g;
+  double s_e, s_eps, s_q, sT_e, sT_nu;
+} pm_lattice;
+
+/* Defaults: nx = ny = 64, n = 1, Da = +inf, Ra = 1e3, Pr = 10, eps = 1,
+ * mach = 0.1, nu_lo = 0.1, nu_hi = 10, PM_CLAMP_NU, PM_FP32, forchheimer = 1,
+ * has_logda = 0, paper rates, no body force, T_init = 0.5. */
+int pm_params_default(pm_params* p);
+
+/* Validate p and describe the lattice it maps to.  Host only.  PM_EINVAL if
+ * any tau would be <= 1/2, a bound is inverted, or a value is out of range. */
+int pm_lattice_of(const pm_params* p, pm_lattice* out);
+
+/* Device workspace size (bytes) that pm_init needs for p. */
+int pm_workspace_bytes(const pm_params* p, size_t* bytes);
+
+/* Create a context: validates p, carves the caller's device workspace
+ * dev_ws (at least pm_workspace_bytes, 256-byte aligned, on the current
+ * device), and enqueues the rest-state initialisation (rho = 1, u = 0,
+ * theta = T_init) on hip_stream (a hipStream_t; NULL = default stream).
+ * The workspace must stay allocated until pm_destroy. */
+int pm_init(const pm_params* p, void* dev_ws, size_t ws_bytes, void* hip_stream,
+            pm_ctx** out);
+
+/* Release the host context (never frees the caller's workspace). */
+void pm_destroy(pm_ctx* ctx);
+
+/* Per-cell log10(Da) plane [ny][nx] in device memory (dtype PM_FP32 or
+ * PM_FP64), copied into the workspace; K(x) = 10^logDa(x) N^2.  Requires
+ * has_logda = 1.  Async. */
+int pm_set_logda(pm_ctx* ctx, const void* dev_plane, int dtype);
+
+/* Advance k >= 0 time steps (one step = stream + collide of every node for
+ * both populations).  Async. */
+int pm_step(pm_ctx* ctx, int64_t k);
+
+/* Steps done since pm_init / the last pm_set_populations or pm_load_state. */
+int pm_steps_done(const pm_ctx* ctx, int64_t* steps);
+
+/* Hot-wall average Nusselt number of the current state, Eq. (24), summed in
+ * FP64 in a fixed order.  Synchronises.  PM_EDIVERGED if not finite. */
+int pm_nu(pm_ctx* ctx, double* nu_out);
+
+/* Steady-state residual: r = max over nodes of |theta - theta_snapshot|
+ * (FP64), then snapshot := theta.  The snapshot is taken at pm_init.
+ * Synchronises.  PM_EDIVERGED (with *r_out = +inf) if a NaN/Inf is met. */
+int pm_residual(pm_ctx* ctx, double* r_out);
+
+/* Run in chunks of check_every steps, calling pm_residual after each, until
+ * r < tol or max_steps steps were taken by this call.  *steps_out = steps
+ * taken by this call, *r_out = last residual. */
+int pm_run_to_steady(pm_ctx* ctx, double tol, int64_t check_every, int64_t max_steps,
+                     int64_t* steps_out, double* r_out);
+
+/* Nondimensional fields of the current state into caller device buffers
+ * [ny][nx] of dtype PM_FP32 / PM_FP64: U = u/U_lb, V = v/U_lb (u is the
+ * porous velocity of the update), theta.  Any pointer may be NULL.  Async. */
+int pm_fields(pm_ctx* ctx, void* U, void* V, void* theta, int dtype);
+
+/* Local lattice viscosity nu(x) of the current state [ny][nx].  Async. */
+int pm_viscosity(pm_ctx* ctx, void* nu, int dtype);
+
+/* Pre-collision populations of the current state, absolute values:
+ * f [9][ny][nx], g [5][ny][nx] in caller device buffers of dtype.  Async. */
+int pm_get_populations(pm_ctx* ctx, void* f, void* g, int dtype);
+
+/* Replace the state by the given pre-collision populations (same layout);
+ * resets the step count to 0.  Async. */
+int pm_set_populations(pm_ctx* ctx, const void* f, const void* g, int dtype);
+
+/* Raw state checkpoint: pm_state_bytes gives the size; save/load copy the
+ * population planes plus the step count between the workspace and a caller
+ * device buffer.  Loading restores the step count.  Async. */
+int pm_state_bytes(const pm_ctx* ctx, size_t* bytes);
+int pm_save_state(pm_ctx* ctx, void* dev_dst, size_t bytes);
+int pm_load_state(pm_ctx* ctx, const void* dev_src, size_t bytes);
+
+/* Read+write bandwidth probe: copies `bytes` (multiple of 16) from src to dst
+ * with the library's streaming copy kernel on hip_stream.  Used to measure
+ * the achievable HBM ceiling and to calibrate traffic counters.  Async. */
+int pm_copy_probe(const void* src, void* dst, size_t bytes, void* hip_stream);
+
+const char* pm_strerror(int code);
+const char* pm_last_error(const pm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,135 @@
+"""ctypes binding of libpmlbm.so (the C ABI declared in include/pmlbm.h).
+
+Argument marshalling only: every step of the update runs in the HIP kernels
+of the shared library.  If the library is missing this module raises at
+import time -- there is no fallback implementation.
+"""
+import ctypes as C
+import math
+import os
+
+# torch must load its HIP runtime before libpmlbm.so resolves libamdhip64:
+# the library then binds to the same runtime as the device memory and streams
+# it is handed (a second runtime in the process would see no device).
+import torch  # noqa: F401
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpmlbm.so")
+
+PM_OK, PM_EINVAL, PM_EDEVICE, PM_EDIVERGED, PM_ESTATE = 0, -1, -2, -3, -4
+PM_FP32, PM_FP64 = 0, 1
+PM_CLAMP_NU, PM_CLAMP_GAMMA = 0, 1
+
+# every symbol the header declares, in declaration order
+EXPORTS = [
+    "pm_params_default", "pm_lattice_of", "pm_workspace_bytes", "pm_init", "pm_destroy",
+    "pm_set_logda", "pm_step", "pm_steps_done", "pm_nu", "pm_residual", "pm_run_to_steady",
+    "pm_fields", "pm_viscosity", "pm_get_populations", "pm_set_populations",
+    "pm_state_bytes", "pm_save_state", "pm_load_state", "pm_copy_probe", "pm_strerror",
+    "pm_last_error",
+]
+
+
+class PmParams(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32),
+                ("periodic_x", C.c_int32), ("periodic_y", C.c_int32),
+                ("n", C.c_double), ("Da", C.c_double), ("Ra", C.c_double), ("Pr", C.c_double),
+                ("eps", C.c_double), ("mach", C.c_double),
+                ("nu_lo", C.c_double), ("nu_hi", C.c_double),
+                ("clamp_mode", C.c_int32), ("dtype", C.c_int32), ("forchheimer", C.c_int32),
+                ("has_logda", C.c_int32),
+                ("s_e", C.c_double), ("s_eps", C.c_double), ("s_q", C.c_double),
+                ("sT_e", C.c_double), ("sT_nu", C.c_double),
+                ("gx", C.c_double), ("gy", C.c_double), ("T_init", C.c_double)]
+
+
+class PmLattice(C.Structure):
+    _fields_ = [(k, C.c_double) for k in (
+        "U_lb", "nu0", "nu_min", "nu_max", "gamma_scale", "eps", "K", "Feps", "gbeta", "T_m",
+        "alpha", "tau0", "tau_min", "tau_max", "tau_g", "s_e", "s_eps", "s_q", "sT_e", "sT_nu")]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class PmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is not built; run `python -c \"import __graft_entry__ as g; g.build()\"` "
+            "(or python paper_2011_15073_amd/build.py) first")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, sz, dbl = C.c_void_p, C.c_int, C.c_int64, C.c_size_t, C.c_double
+    P = C.POINTER
+    sig = {
+        "pm_params_default": ([P(PmParams)], i32),
+        "pm_lattice_of": ([P(PmParams), P(PmLattice)], i32),
+        "pm_workspace_bytes": ([P(PmParams), P(sz)], i32),
+        "pm_init": ([P(PmParams), vp, sz, vp, P(vp)], i32),
+        "pm_destroy": ([vp], None),
+        "pm_set_logda": ([vp, vp, i32], i32),
+        "pm_step": ([vp, i64], i32),
+        "pm_steps_done": ([vp, P(i64)], i32),
+        "pm_nu": ([vp, P(dbl)], i32),
+        "pm_residual": ([vp, P(dbl)], i32),
+        "pm_run_to_steady": ([vp, dbl, i64, i64, P(i64), P(dbl)], i32),
+        "pm_fields": ([vp, vp, vp, vp, i32], i32),
+        "pm_viscosity": ([vp, vp, i32], i32),
+        "pm_get_populations": ([vp, vp, vp, i32], i32),
+        "pm_set_populations": ([vp, vp, vp, i32], i32),
+        "pm_state_bytes": ([vp, P(sz)], i32),
+        "pm_save_state": ([vp, vp, sz], i32),
+        "pm_load_state": ([vp, vp, sz], i32),
+        "pm_copy_probe": ([vp, vp, sz, vp], i32),
+        "pm_strerror": ([i32], C.c_char_p),
+        "pm_last_error": ([vp], C.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    return L
+
+
+lib = _load()
+
+
+def check(rc, ctx=None):
+    if rc != PM_OK:
+        msg = lib.pm_last_error(ctx).decode(errors="replace")
+        raise PmError(rc, f"{lib.pm_strerror(rc).decode()}: {msg}")
+    return rc
+
+
+def make_params(nx, ny=None, *, n=1.0, Da=math.inf, Ra=1e3, Pr=10.0, eps=1.0, mach=0.1,
+                nu_lo=0.1, nu_hi=10.0, clamp_mode=PM_CLAMP_NU, dtype="fp32", forchheimer=1,
+                has_logda=0, s_e=0.0, s_eps=0.0, s_q=0.0, sT_e=0.0, sT_nu=0.0, gx=0.0, gy=0.0,
+                T_init=0.5, periodic_x=0, periodic_y=0) -> PmParams:
+    p = PmParams()
+    check(lib.pm_params_default(C.byref(p)))
+    p.nx, p.ny = int(nx), int(nx if ny is None else ny)
+    p.periodic_x, p.periodic_y = int(periodic_x), int(periodic_y)
+    p.n, p.Da, p.Ra, p.Pr, p.eps, p.mach = n, Da, Ra, Pr, eps, mach
+    p.nu_lo, p.nu_hi, p.clamp_mode = nu_lo, nu_hi, int(clamp_mode)
+    p.dtype = {"fp32": PM_FP32, "fp64": PM_FP64, PM_FP32: PM_FP32, PM_FP64: PM_FP64}[dtype]
+    p.forchheimer, p.has_logda = int(forchheimer), int(has_logda)
+    p.s_e, p.s_eps, p.s_q, p.sT_e, p.sT_nu = s_e, s_eps, s_q, sT_e, sT_nu
+    p.gx, p.gy, p.T_init = gx, gy, T_init
+    return p
+
+
+def lattice_of(p: PmParams) -> PmLattice:
+    out = PmLattice()
+    check(lib.pm_lattice_of(C.byref(p), C.byref(out)))
+    return out
+
+
+def workspace_bytes(p: PmParams) -> int:
+    n = C.c_size_t()
+    check(lib.pm_workspace_bytes(C.byref(p), C.byref(n)))
+    return n.value

@@ -1,0 +1,79 @@
+// pm_internal.h -- device-side parameter block and kernel launchers of the
+// gfx950 lattice Boltzmann library (internal; the public ABI is pmlbm.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace pm {
+
+// Everything one node update needs, already converted to the compute type.
+// Populations are stored shifted: df_q = f_q - w_q and dg_q = g_q - w_q T_ref
+// (T_ref = 1/2), which keeps FP32 resolution on the small deviations from the
+// rest state.
+template <typename T>
+struct KParams {
+  T* f;            // 9 planes of P elements
+  T* g;            // 5 planes
+  const T* logda;  // per-cell log10(Da) plane or nullptr
+  int64_t P;       // plane pitch in elements
+  int nx, ny;
+  int px, py;      // periodic axes
+  // viscosity (power law, Eq. 21)
+  T nu_newt;       // clamped nu0, the Newtonian value
+  T nu_min, nu_max;
+  T y_lo, y_hi;    // log2 of nu_min, nu_max
+  T lc0;           // log2 nu0 + (n - 1) log2 gamma_scale
+  T nm1, inv_n;    // n - 1, 1 / n
+  T tol;           // Newton tolerance on log2(nu)
+  int max_it;
+  // porous medium
+  T eps, inv_eps, invK, invsK, Feps, inv_Kscale;
+  // body forces: G = (gx, gy + gbeta (T - T_m))
+  T gbeta, dTm;    // dTm = T_m - T_ref
+  T gx, gy;
+  // relaxation rates
+  T s_e, s_eps, s_q, s_g, sT_e, sT_nu;
+  // thermal walls in shifted form: 2 w_1 (T_wall - T_ref)
+  T hotc, coldc;
+  T T_ref;
+  T inv_U;         // 1 / U_lb
+};
+
+struct Launch {
+  hipStream_t stream;
+  int tiles_x;     // row tiles of TILE nodes
+  int ntiles;      // tiles_x * ny
+};
+
+constexpr int TILE = 256;       // nodes per workgroup (one row segment)
+constexpr int RED_BLOCKS = 1024; // partial-result slots of the residual
+
+// parity 0: state in natural layout; 1: after an odd number of steps
+template <typename T>
+hipError_t launch_step(const KParams<T>& p, const Launch& L, int parity, bool pow, bool logda);
+template <typename T>
+hipError_t launch_init(const KParams<T>& p, const Launch& L, T dg_init);
+template <typename T>
+hipError_t launch_nu(const KParams<T>& p, const Launch& L, int parity, double* out);
+template <typename T>
+hipError_t launch_residual(const KParams<T>& p, const Launch& L, int parity, T* snap,
+                           double* partial, double* out, int take_snapshot_only);
+template <typename T>
+hipError_t launch_fields(const KParams<T>& p, const Launch& L, int parity, bool pow, bool logda,
+                         void* U, void* V, void* th, void* nu, int out_fp64);
+template <typename T>
+hipError_t launch_get_pop(const KParams<T>& p, const Launch& L, int parity, void* f, void* g,
+                          int out_fp64);
+template <typename T>
+hipError_t launch_set_pop(const KParams<T>& p, const Launch& L, const void* f, const void* g,
+                          int in_fp64);
+template <typename T>
+hipError_t launch_set_logda(const KParams<T>& p, const Launch& L, T* dst, const void* src,
+                            int in_fp64);
+hipError_t launch_write_header(void* dst, int64_t steps, uint64_t tag, hipStream_t s);
+hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, hipStream_t s);
+
+}  // namespace pm

@@ -1,0 +1,46 @@
+"""Seeded synthetic inputs shared by the tests, the smoke check and the
+benchmark.  Random draws only -- none of the method's arithmetic lives here.
+
+Recipes (numpy.random.default_rng):
+  * sweep grid sides: rng(seed).choice([128, 192, 256, 384, 512], 27), one
+    per case in itertools.product(n, Da, Ra) order;
+  * per-cell log10(Da) field: rng(seed).uniform(-3, -1, (N, N)), float64;
+  * finite-difference probe cells: rng(seed + 1).choice(N*N, 16, replace=False);
+  * random population states (parity tests): rest weights times
+    (1 + amp * standard normal), thermal weights times (T0 + amp_T * normal).
+"""
+import itertools
+
+import numpy as np
+
+W9 = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+W5 = np.array([1 / 3] + [1 / 6] * 4)
+
+SWEEP_N = (0.6, 0.8, 1.0)
+SWEEP_DA = (1e-3, 1e-2, 1e-1)
+SWEEP_RA = (1e3, 1e4, 1e5)
+SWEEP_SIDES = (128, 192, 256, 384, 512)
+
+
+def sweep_cases(seed=0):
+    """The 27 (n, Da, Ra, N) cases of the parameter sweep."""
+    rng = np.random.default_rng(seed)
+    sides = rng.choice(SWEEP_SIDES, 27)
+    combos = list(itertools.product(SWEEP_N, SWEEP_DA, SWEEP_RA))
+    return [dict(n=n, Da=da, Ra=ra, N=int(s)) for (n, da, ra), s in zip(combos, sides)]
+
+
+def logda_field(N, seed=0, lo=-3.0, hi=-1.0):
+    return np.random.default_rng(seed).uniform(lo, hi, (N, N))
+
+
+def fd_cells(N, seed=1, k=16):
+    return np.random.default_rng(seed).choice(N * N, k, replace=False)
+
+
+def random_state(nx, ny, seed, amp=0.05, T0=0.5, amp_T=0.2):
+    """Random pre-collision populations f [9, ny, nx], g [5, ny, nx]."""
+    rng = np.random.default_rng(seed)
+    f = W9[:, None, None] * (1 + amp * rng.standard_normal((9, ny, nx)))
+    g = W5[:, None, None] * (T0 + amp_T * rng.standard_normal((5, ny, nx)))
+    return f, g

@@ -1,0 +1,95 @@
+"""CPU-side checks of the C ABI: the shared library loads, exports every
+symbol include/pmlbm.h declares, validates parameters, and its host-side
+parameter mapping agrees with the oracle's independent implementation of the
+same mapping.  No GPU calls."""
+import math
+import os
+import re
+
+import pytest
+
+import oracle as O
+import paper_2011_15073_amd as P
+from paper_2011_15073_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    text = open(os.path.join(ROOT, "include", "pmlbm.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pm_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    syms = header_symbols()
+    assert len(syms) >= 20
+    for s in syms:
+        assert hasattr(_lib.lib, s), f"{s} declared in pmlbm.h but not exported"
+    assert sorted(_lib.EXPORTS) == syms
+
+
+def test_params_struct_layout_matches_header():
+    # the ctypes mirror must have the same field order as the C struct
+    text = open(os.path.join(ROOT, "include", "pmlbm.h")).read()
+    body = text[text.index("typedef struct {\n  int32_t nx, ny;"):text.index("} pm_params;")]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    names = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl or decl.startswith("typedef"):
+            decl = decl.split("{", 1)[-1].strip()
+        if not decl:
+            continue
+        parts = decl.split(None, 1)
+        names += [n.strip() for n in parts[1].split(",")]
+    assert names == [f for f, _ in _lib.PmParams._fields_]
+
+
+@pytest.mark.parametrize("case", [
+    dict(N=64, n=1.0, Da=0.1, Ra=1e3, Pr=10.0, eps=0.6),
+    dict(N=256, n=0.6, Da=1e-3, Ra=1e5, Pr=10.0, eps=0.6),
+    dict(N=4096, n=0.8, Da=1e-2, Ra=1e5, Pr=10.0, eps=0.6),
+    dict(N=160, n=1.4, Da=math.inf, Ra=1e5, Pr=100.0, eps=1.0, forchheimer=0),
+    dict(N=48, n=0.7, Da=1e-2, Ra=1e4, Pr=6.2, eps=0.6, clamp_mode=1, nu_lo=0.01, nu_hi=1e6),
+])
+def test_host_mapping_matches_oracle(case):
+    case = dict(case)
+    N = case.pop("N")
+    p = P.make_params(N, **case)
+    L = P.lattice_of(p)
+    o = O.map_physics(O.physics(N, **case))
+    for k in ("U_lb", "nu0", "nu_min", "nu_max", "gamma_scale", "eps", "Feps", "gbeta",
+              "alpha", "s_e", "s_eps", "s_q", "sT_e", "sT_nu"):
+        a, b = getattr(L, k), getattr(o, k)
+        assert a == pytest.approx(b, rel=1e-14, abs=0.0), k
+    assert (math.isinf(L.K) and math.isinf(o.K)) or L.K == pytest.approx(o.K, rel=1e-15)
+    assert L.tau_g == pytest.approx(3 * o.alpha + 0.5, rel=1e-15)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(nx=1), dict(eps=0.0), dict(eps=1.2), dict(n=0.0), dict(Ra=-1.0), dict(Da=0.0),
+    dict(mach=0.0), dict(nu_lo=2.0), dict(nu_lo=0.5, nu_hi=0.4), dict(dtype=7),
+    dict(s_q=2.5),
+])
+def test_invalid_parameters_are_rejected(bad):
+    p = P.make_params(32)
+    for k, v in bad.items():
+        setattr(p, k, v)
+    with pytest.raises(P.PmError) as e:
+        P.lattice_of(p)
+    assert e.value.code == _lib.PM_EINVAL
+    assert _lib.lib.pm_last_error(None).decode()
+
+
+def test_workspace_size_covers_planes():
+    p = P.make_params(4096, 4096, dtype="fp32")
+    assert P.workspace_bytes(p) >= 15 * 4096 * 4096 * 4
+    p64 = P.make_params(33, 17, dtype="fp64", has_logda=1)
+    assert P.workspace_bytes(p64) >= 16 * 33 * 17 * 8
+    assert P.workspace_bytes(p64) % 256 == 0
+
+
+def test_strerror_codes():
+    for code in (0, -1, -2, -3, -4):
+        assert _lib.lib.pm_strerror(code)

@@ -1,0 +1,223 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs.
+
+Bars (field error = max|X_gpu - X_ref| / max|X_ref| for X in U, V, theta;
+Nusselt number |dNu|/Nu):
+  * FP64 kernels: <= 1e-11;
+  * FP32 storage and arithmetic (FP64 reductions): <= 1e-4;
+  * single steps from random non-equilibrium states, FP64: populations agree
+    to 1e-13 absolute (every branch of the collision, walls and viscosity).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2011_15073_amd import inputs
+from pairs import compare_fields, compare_nu, gpu_for, gpu_fields, oracle_for, rel_err
+
+pytestmark = pytest.mark.gpu
+
+CFG0 = dict(n=1.0, Da=0.1, Ra=1e3, Pr=10.0, eps=0.6)
+TOL = {"fp64": 1e-11, "fp32": 1e-4}
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+def test_cavity_64_newtonian_20000_steps(dtype):
+    """The 64x64 porous cavity, Newtonian, Da = 0.1, Ra = 1e3, Pr = 10,
+    eps = 0.6, 20000 steps from rest."""
+    log("case: 64^2", dtype, CFG0)
+    cav = gpu_for(64, dtype=dtype, **CFG0)
+    cav.step(20000)
+    orc = oracle_for(64, **CFG0).step(20000)
+    errs = compare_fields(cav, orc)
+    dnu = compare_nu(cav, orc)
+    log(dtype, errs, dnu, cav.nu())
+    assert max(errs.values()) <= TOL[dtype] and dnu <= TOL[dtype]
+
+
+RANDOM_CASES = [
+    dict(n=1.0, Da=0.1, Ra=1e3, Pr=10.0, eps=0.6),
+    dict(n=0.6, Da=1e-3, Ra=1e5, Pr=10.0, eps=0.6),
+    dict(n=1.4, Da=math.inf, Ra=1e5, Pr=100.0, eps=1.0, forchheimer=0),
+    dict(n=0.7, Da=1e-2, Ra=1e4, Pr=6.2, eps=0.6, clamp_mode=1, nu_lo=0.01, nu_hi=1e6),
+    dict(n=0.8, Da=1e-2, Ra=1e5, Pr=10.0, eps=0.6, periodic_x=1),
+    dict(n=0.5, Da=1e-2, Ra=1e4, Pr=10.0, eps=0.5, periodic_y=1, gx=1e-5, gy=-2e-5),
+    dict(n=1.2, Da=1e-2, Ra=1e4, Pr=10.0, eps=0.7, periodic_x=1, periodic_y=1),
+]
+
+
+@pytest.mark.parametrize("ci", range(len(RANDOM_CASES)))
+@pytest.mark.parametrize("logda", [False, True])
+def test_random_state_steps_fp64(ci, logda):
+    """Random non-equilibrium states on a ragged 37 x 21 grid: populations
+    after 1, 2 and 5 steps (both AA parities, every wall and corner)."""
+    kw = RANDOM_CASES[ci]
+    nx, ny = 37, 21
+    f0, g0 = inputs.random_state(nx, ny, seed=100 + ci, amp=0.05)
+    ld = inputs.logda_field(nx, seed=ci)[:ny, :nx] if logda else None
+    log("case:", ci, kw, "logda" if logda else "")
+    cav = gpu_for(nx, ny, dtype="fp64", logda=ld, **kw)
+    cav.set_populations(torch.from_numpy(f0), torch.from_numpy(g0))
+    orc = oracle_for(nx, ny, logda=ld, **kw)
+    orc.set_state(f0, g0)
+    for k in (1, 1, 3):
+        cav.step(k)
+        orc.step(k)
+        fg, gg = (t.cpu().numpy() for t in cav.populations(torch.float64))
+        fr, gr = orc.state()
+        ef, eg = np.abs(fg - fr).max(), np.abs(gg - gr).max()
+        log("  after", orc.steps, "steps: pop err", ef, eg)
+        assert ef <= 1e-13 and eg <= 1e-13
+    nu_g = cav.viscosity(torch.float64).cpu().numpy()
+    assert rel_err(nu_g, orc.macros()["nu"]) <= 1e-12
+
+
+SIZES = [(8, 8), (33, 33), (96, 96), (257, 40), (300, 37)]
+
+
+@pytest.mark.parametrize("size", SIZES)
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+@pytest.mark.parametrize("n", [0.5, 1.0, 1.5])
+def test_ragged_grids_and_step_counts(size, dtype, n):
+    """Grids that are not multiples of the 256-node row tile, non-square,
+    odd and even step counts.  Ra = 1e3 and the clamp [0.5, 2] nu0 keep
+    tau >= 0.6 so the transient stays well conditioned (as tau -> 1/2 the
+    flow amplifies round-off differences); early fields are tiny, so errors
+    are taken relative to max(max|ref|, 1e-2)."""
+    nx, ny = size
+    kw = dict(n=n, Da=1e-2, Ra=1e3, Pr=6.2, eps=0.6, nu_lo=0.5, nu_hi=2.0)
+    log("case:", size, dtype, kw)
+    cav = gpu_for(nx, ny, dtype=dtype, **kw)
+    orc = oracle_for(nx, ny, **kw)
+    done = 0
+    for k in (1, 1, 499, 499):
+        cav.step(k)
+        orc.step(k)
+        done += k
+        Ug, Vg, Tg = gpu_fields(cav)
+        Ur, Vr, Tr = orc.fields()
+        errs = {name: float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-2))
+                for name, a, b in (("U", Ug, Ur), ("V", Vg, Vr), ("theta", Tg, Tr))}
+        dnu = compare_nu(cav, orc)
+        log("  steps", done, errs, dnu)
+        assert max(errs.values()) <= TOL[dtype] and dnu <= TOL[dtype]
+
+
+def test_powerlaw_cavity_fp32():
+    kw = dict(n=0.6, Da=1e-3, Ra=1e5, Pr=10.0, eps=0.6)
+    cav = gpu_for(64, dtype="fp32", **kw)
+    orc = oracle_for(64, **kw)
+    cav.step(6000)
+    orc.step(6000)
+    errs = compare_fields(cav, orc)
+    dnu = compare_nu(cav, orc)
+    log("power-law fp32", errs, dnu)
+    assert max(errs.values()) <= 1e-4 and dnu <= 1e-4
+
+
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+def test_residual_matches_temperature_change(dtype):
+    kw = dict(n=0.8, Da=1e-2, Ra=1e4, Pr=10.0, eps=0.6)
+    cav = gpu_for(40, dtype=dtype, **kw)
+    orc = oracle_for(40, **kw)
+    T0 = orc.fields()[2]
+    for _ in range(2):
+        cav.step(1000)
+        orc.step(1000)
+        T1 = orc.fields()[2]
+        r_ref = np.abs(T1 - T0).max()
+        r = cav.residual()
+        log(dtype, "residual", r, r_ref)
+        # theta is O(1): the residual inherits the field bar as an absolute bound
+        assert abs(r - r_ref) <= (1e-13 if dtype == "fp64" else 1e-4)
+        T0 = T1
+    # run_to_steady stops at the first check with r < tol
+    r, steps = cav.run_to_steady(tol=1e-3, check_every=500, max_steps=20000)
+    assert r < 1e-3 and steps % 500 == 0 and steps <= 20000
+
+
+def test_graph_replay_equals_single_launches():
+    kw = dict(n=0.7, Da=1e-2, Ra=1e5, Pr=10.0, eps=0.6)
+    a = gpu_for(50, 30, dtype="fp32", **kw)
+    b = gpu_for(50, 30, dtype="fp32", **kw)
+    a.step(3)
+    a.step(300)  # odd start parity, graph chunks plus a tail
+    for _ in range(303):
+        b.step(1)
+    fa, ga = a.populations(torch.float32)
+    fb, gb = b.populations(torch.float32)
+    assert torch.equal(fa, fb) and torch.equal(ga, gb)
+    assert a.steps == b.steps == 303
+
+
+def test_checkpoint_resume_is_bitwise():
+    kw = dict(n=0.6, Da=1e-3, Ra=1e5, Pr=10.0, eps=0.6)
+    a = gpu_for(48, dtype="fp32", **kw)
+    a.step(777)
+    snap = a.save_state()
+    a.step(500)
+    b = gpu_for(48, dtype="fp32", **kw)
+    b.load_state(snap)
+    assert b.steps == 777
+    b.step(500)
+    fa, ga = a.populations(torch.float32)
+    fb, gb = b.populations(torch.float32)
+    assert torch.equal(fa, fb) and torch.equal(ga, gb)
+    c = gpu_for(40, dtype="fp32", **kw)
+    with pytest.raises(Exception):
+        c.load_state(snap)
+
+
+def test_runs_are_deterministic():
+    kw = dict(n=0.6, Da=1e-3, Ra=1e5, Pr=10.0, eps=0.6)
+    outs = []
+    for _ in range(2):
+        c = gpu_for(130, dtype="fp32", **kw)
+        c.step(2000)
+        outs.append((c.nu(), c.residual(), [t.cpu() for t in c.fields(torch.float32)]))
+    assert outs[0][0] == outs[1][0] and outs[0][1] == outs[1][1]
+    assert all(torch.equal(x, y) for x, y in zip(outs[0][2], outs[1][2]))
+
+
+def test_nan_is_reported_as_divergence():
+    kw = dict(n=1.0, Da=0.1, Ra=1e3, Pr=10.0, eps=0.6)
+    c = gpu_for(16, dtype="fp32", **kw)
+    f, g = inputs.random_state(16, 16, seed=5, amp=0.0, amp_T=0.0)
+    g[2, 7, 0] = np.nan  # planted from the host in the hot-wall column
+    c.set_populations(torch.from_numpy(f), torch.from_numpy(g))
+    c.step(3)
+    with pytest.raises(Exception) as e:
+        c.residual()
+    assert getattr(e.value, "code", None) == -3
+    with pytest.raises(Exception):
+        c.nu()
+
+
+def test_full_size_4096_fp32_sampled():
+    """The 4096^2 throughput workload (FP32, n = 0.8, Da = 1e-2, Ra = 1e5,
+    eps = 0.6) in the launch configuration the benchmark times, after 16
+    steps, against the oracle at the same size."""
+    kw = dict(n=0.8, Da=1e-2, Ra=1e5, Pr=10.0, eps=0.6)
+    N, steps = 4096, 16
+    log("case: 4096^2 fp32", kw, steps, "steps")
+    cav = gpu_for(N, dtype="fp32", **kw)
+    cav.step(steps)
+    Ug, Vg, Tg = gpu_fields(cav)
+    nu_g = cav.nu()
+    del cav
+    torch.cuda.empty_cache()
+    orc = oracle_for(N, **kw).step(steps)
+    Ur, Vr, Tr = orc.fields()
+    errs = dict(U=rel_err(Ug, Ur), V=rel_err(Vg, Vr), theta=rel_err(Tg, Tr))
+    dnu = abs(nu_g - orc.nu_bar()) / orc.nu_bar()
+    log("4096^2:", errs, dnu)
+    assert max(errs.values()) <= 1e-4 and dnu <= 1e-4
+    # far from the walls the fluid is still exactly at rest after 16 steps
+    assert np.all(Ug[100:-100, 100:-100] == 0.0) and np.all(Tg[100:-100, 100:-100] == 0.5)
