@@ -42,7 +42,7 @@ Layout layout_of(const pm_params& p) {
   Layout L{};
   L.elem = p.dtype == PM_FP64 ? 8 : 4;
   const size_t n = (size_t)p.nx * (size_t)p.ny;
-  L.P = (n + 63) / 64 * 64;
+  L.P = (n + 63) / 64 * 64 + PM_PITCH_SKEW;
   size_t o = 0;
   L.off_f = o;
   o = align_up(o + 9 * L.P * L.elem);

@@ -48,7 +48,13 @@ struct Launch {
   int ntiles;      // tiles_x * ny
 };
 
-constexpr int TILE = 256;       // nodes per workgroup (one row segment)
+#ifndef PM_TILE
+#define PM_TILE 256
+#endif
+#ifndef PM_PITCH_SKEW
+#define PM_PITCH_SKEW 0
+#endif
+constexpr int TILE = PM_TILE;   // nodes per workgroup (one row segment)
 constexpr int RED_BLOCKS = 1024; // partial-result slots of the residual
 
 // parity 0: state in natural layout; 1: after an odd number of steps

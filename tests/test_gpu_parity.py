@@ -55,13 +55,15 @@ RANDOM_CASES = [
 
 @pytest.mark.parametrize("ci", range(len(RANDOM_CASES)))
 @pytest.mark.parametrize("logda", [False, True])
-def test_random_state_steps_fp64(ci, logda):
-    """Random non-equilibrium states on a ragged 37 x 21 grid: populations
-    after 1, 2 and 5 steps (both AA parities, every wall and corner)."""
+@pytest.mark.parametrize("grid", [(37, 21), (200, 23)])
+def test_random_state_steps_fp64(ci, logda, grid):
+    """Random non-equilibrium states on ragged grids: populations after 1, 2
+    and 5 steps (both AA parities, every wall and corner; on the 200-wide grid
+    the interior waves take the branch-free path of the streaming step)."""
     kw = RANDOM_CASES[ci]
-    nx, ny = 37, 21
+    nx, ny = grid
     f0, g0 = inputs.random_state(nx, ny, seed=100 + ci, amp=0.05)
-    ld = inputs.logda_field(nx, seed=ci)[:ny, :nx] if logda else None
+    ld = inputs.logda_field(max(nx, ny), seed=ci)[:ny, :nx].copy() if logda else None
     log("case:", ci, kw, "logda" if logda else "")
     cav = gpu_for(nx, ny, dtype="fp64", logda=ld, **kw)
     cav.set_populations(torch.from_numpy(f0), torch.from_numpy(g0))
