@@ -85,6 +85,64 @@ def cpu_baseline(budget_s=15.0):
                       f"{dt:.1f} s"}
 
 
+def sweep_main(args):
+    """The 27-case (n, Da, Ra) sweep with seeded uneven grid sides: one batched
+    sweep (tuned schedule, graph-replayed chunks) against the same cases run one
+    after another with the single-case solver; cases/s for both, and a bitwise
+    comparison of every case's final populations."""
+    import torch
+    import paper_2011_15073_amd as P
+    from paper_2011_15073_amd import inputs
+
+    dt = args.sweep_dtype
+    cs = inputs.sweep_cases(0)
+    cases = [dict(nx=c["N"], n=c["n"], Da=c["Da"], Ra=c["Ra"], Pr=10.0, eps=0.6, dtype=dt) for c in cs]
+    log(f"sweep: {len(cases)} cases, sides {[c['N'] for c in cs]}, {dt}, tol {args.sweep_tol}")
+    order, times = P.tune(cases)
+    log(f"sweep: schedule {order} ({ {k: round(v, 1) for k, v in times.items()} } us/step)")
+    sw = P.Sweep(cases, order=order)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    steps, res = sw.run(tol=args.sweep_tol, check_every=1000, max_steps=args.sweep_cap,
+                        progress=lambda nl, st: log(f"sweep: batched, {nl} live, max steps {max(st)}"))
+    torch.cuda.synchronize()
+    t_batched = time.perf_counter() - t0
+    nupd = sum(s_ * c["N"] ** 2 for s_, c in zip(steps, cs))
+    log(f"sweep: batched {t_batched:.2f} s, {nupd / t_batched / 1e6:.0f} MLUPS")
+    t_seq, same = 0.0, 0
+    tdt = torch.float64 if dt == "fp64" else torch.float32
+    for i, (kw, c) in enumerate(zip(cases, cs)):
+        kw = dict(kw)
+        nx = kw.pop("nx")
+        cav = P.Cavity(nx, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r, st = cav.run_to_steady(tol=args.sweep_tol, check_every=1000, max_steps=args.sweep_cap)
+        torch.cuda.synchronize()
+        t_seq += time.perf_counter() - t0
+        fa, ga = cav.populations(tdt)
+        fb, gb = sw.case(i).populations(tdt)
+        eq = st == steps[i] and torch.equal(fa, fb) and torch.equal(ga, gb)
+        same += int(eq)
+        log(f"sweep: case {i} N={c['N']} n={c['n']} Da={c['Da']:.0e} Ra={c['Ra']:.0e}: "
+            f"{st} steps, r {r:.2e}, Nu {cav.nu():.6f}, bitwise equal {eq}")
+        del cav
+    print(json.dumps({
+        "metric": "sweep cases/s", "value": round(len(cases) / t_batched, 4), "unit": "cases/s",
+        "n_gpus": 1, "higher_is_better": True, "dtype": "f64" if dt == "fp64" else "f32",
+        "data": "synthetic",
+        "config": {"workload": "27-case sweep n in {0.6,0.8,1.0} x Da in {1e-3,1e-2,1e-1} x "
+                               "Ra in {1e3,1e4,1e5}, eps=0.6, Pr=10, sides drawn from "
+                               "{128,192,256,384,512} (seed 0)", "tol": args.sweep_tol,
+                   "check_every": 1000, "max_steps": args.sweep_cap, "schedule": order},
+        "batched_s": round(t_batched, 3), "sequential_s": round(t_seq, 3),
+        "sequential_cases_per_s": round(len(cases) / t_seq, 4),
+        "speedup_vs_sequential": round(t_seq / t_batched, 3),
+        "node_updates": nupd, "batched_MLUPS": round(nupd / t_batched / 1e6, 1),
+        "cases_bitwise_equal_to_sequential": f"{same}/{len(cases)}",
+        "steps_per_case": steps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,11 +150,20 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--roofline-steps", type=int, default=400)
+    ap.add_argument("--sweep", action="store_true",
+                    help="run the 27-case batched-sweep benchmark instead")
+    ap.add_argument("--sweep-dtype", default="fp64", choices=["fp32", "fp64"])
+    ap.add_argument("--sweep-tol", type=float, default=1e-8)
+    ap.add_argument("--sweep-cap", type=int, default=3_000_000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the path is measured on one GPU's share; see the sharding notes)", file=sys.stderr)
         sys.exit(2)
+
+    if args.sweep:
+        sweep_main(args)
+        return
 
     import torch
     import paper_2011_15073_amd as P

@@ -170,6 +170,55 @@ int pm_load_state(pm_ctx* ctx, const void* dev_src, size_t bytes);
  * the achievable HBM ceiling and to calibrate traffic counters.  Async. */
 int pm_copy_probe(const void* src, void* dst, size_t bytes, void* hip_stream);
 
+/* ---- Batched parameter sweep ----
+ * Many independent cavities (e.g. the (n, Da, Ra) grid of the paper's
+ * parametric study, Table 2, with uneven grid sides) advanced together: one
+ * launch per time step covers every row tile of every case still running,
+ * and a chunk of check_every steps plus the per-case residual test is
+ * replayed as one HIP graph.  Each case stops at the first check with
+ * residual < tol (or at max_steps, or on NaN/Inf) exactly as
+ * pm_run_to_steady would stop it, and is then skipped.  The per-node
+ * arithmetic is the single-case kernel's, so every case ends bitwise equal to
+ * the same case run alone.  All cases must share one dtype; per-cell log-Da
+ * planes are not supported.  The workspace (caller-owned device memory,
+ * 256-byte aligned) holds every case's planes plus the case table,
+ * schedule, flags and partial results. */
+typedef struct pm_sweep pm_sweep;
+
+#define PM_ORDER_CASE 0       /* schedule row tiles case after case, in input order */
+#define PM_ORDER_LARGEST 1    /* case after case, largest case first */
+#define PM_ORDER_INTERLEAVE 2 /* round-robin over the cases, tile by tile */
+
+int pm_sweep_workspace_bytes(const pm_params* cases, int ncases, size_t* bytes);
+/* Validates every case, creates one context per case on its slice of the
+ * workspace (rest state), uploads the case table and the schedule.
+ * Synchronises the stream. */
+int pm_sweep_create(const pm_params* cases, int ncases, void* dev_ws, size_t ws_bytes, void* hip_stream,
+                    pm_sweep** out);
+/* Choose the tile schedule (PM_ORDER_*); used by the autotuner. */
+int pm_sweep_set_order(pm_sweep* s, int order);
+/* Run every live case until it stops (see above).  steps_out[i], r_out[i]
+ * (arrays of ncases, may be NULL): steps taken and last residual of case i.
+ * Returns PM_EDIVERGED if any case stopped on NaN/Inf. */
+int pm_sweep_run(pm_sweep* s, double tol, int64_t check_every, int64_t max_steps, int64_t* steps_out,
+                 double* r_out);
+/* Same as pm_sweep_run but returns after at most max_chunks chunks;
+ * *nlive = cases still running (0: done).  For progress reporting and for
+ * sharing the GPU with other work between chunks. */
+int pm_sweep_advance(pm_sweep* s, double tol, int64_t check_every, int64_t max_steps, int64_t max_chunks,
+                     int* nlive);
+/* Steps taken and last residual of every case so far (arrays of ncases, may
+ * be NULL).  PM_EDIVERGED if a stopped case ended on a NaN/Inf residual. */
+int pm_sweep_status(const pm_sweep* s, int64_t* steps_out, double* r_out);
+/* Advance every live case by k steps with no stopping test (warm-up and
+ * schedule timing).  Synchronises. */
+int pm_sweep_step(pm_sweep* s, int64_t k);
+/* Borrow the context of case i (fields, Nu, populations); owned by the
+ * sweep, valid until pm_sweep_destroy. */
+int pm_sweep_case(pm_sweep* s, int i, pm_ctx** out);
+void pm_sweep_destroy(pm_sweep* s);
+const char* pm_sweep_last_error(const pm_sweep* s);
+
 const char* pm_strerror(int code);
 const char* pm_last_error(const pm_ctx* ctx);
 

@@ -8,6 +8,7 @@ PyTorch supplies device memory and streams only.
 from ._lib import (PM_CLAMP_GAMMA, PM_CLAMP_NU, PM_FP32, PM_FP64, PmError, lattice_of,
                    make_params, workspace_bytes)
 from .cavity import Cavity, copy_probe
+from .sweep import Sweep, tune
 
-__all__ = ["Cavity", "copy_probe", "PmError", "make_params", "lattice_of", "workspace_bytes",
+__all__ = ["Cavity", "Sweep", "tune", "copy_probe", "PmError", "make_params", "lattice_of", "workspace_bytes",
            "PM_FP32", "PM_FP64", "PM_CLAMP_NU", "PM_CLAMP_GAMMA"]

@@ -25,9 +25,14 @@ EXPORTS = [
     "pm_params_default", "pm_lattice_of", "pm_workspace_bytes", "pm_init", "pm_destroy",
     "pm_set_logda", "pm_step", "pm_steps_done", "pm_nu", "pm_residual", "pm_run_to_steady",
     "pm_fields", "pm_viscosity", "pm_get_populations", "pm_set_populations",
-    "pm_state_bytes", "pm_save_state", "pm_load_state", "pm_copy_probe", "pm_strerror",
-    "pm_last_error",
+    "pm_state_bytes", "pm_save_state", "pm_load_state", "pm_copy_probe",
+    "pm_sweep_workspace_bytes", "pm_sweep_create", "pm_sweep_set_order", "pm_sweep_run",
+    "pm_sweep_advance", "pm_sweep_status",
+    "pm_sweep_step", "pm_sweep_case", "pm_sweep_destroy", "pm_sweep_last_error",
+    "pm_strerror", "pm_last_error",
 ]
+
+PM_ORDER_CASE, PM_ORDER_LARGEST, PM_ORDER_INTERLEAVE = 0, 1, 2
 
 
 class PmParams(C.Structure):
@@ -86,6 +91,16 @@ def _load():
         "pm_save_state": ([vp, vp, sz], i32),
         "pm_load_state": ([vp, vp, sz], i32),
         "pm_copy_probe": ([vp, vp, sz, vp], i32),
+        "pm_sweep_workspace_bytes": ([P(PmParams), i32, P(sz)], i32),
+        "pm_sweep_create": ([P(PmParams), i32, vp, sz, vp, P(vp)], i32),
+        "pm_sweep_set_order": ([vp, i32], i32),
+        "pm_sweep_run": ([vp, dbl, i64, i64, P(i64), P(dbl)], i32),
+        "pm_sweep_step": ([vp, i64], i32),
+        "pm_sweep_advance": ([vp, dbl, i64, i64, i64, P(i32)], i32),
+        "pm_sweep_status": ([vp, P(i64), P(dbl)], i32),
+        "pm_sweep_case": ([vp, i32, P(vp)], i32),
+        "pm_sweep_destroy": ([vp], None),
+        "pm_sweep_last_error": ([vp], C.c_char_p),
         "pm_strerror": ([i32], C.c_char_p),
         "pm_last_error": ([vp], C.c_char_p),
     }
@@ -99,9 +114,9 @@ def _load():
 lib = _load()
 
 
-def check(rc, ctx=None):
+def check(rc, ctx=None, errfn=None):
     if rc != PM_OK:
-        msg = lib.pm_last_error(ctx).decode(errors="replace")
+        msg = (errfn or lib.pm_last_error)(ctx).decode(errors="replace")
         raise PmError(rc, f"{lib.pm_strerror(rc).decode()}: {msg}")
     return rc
 

@@ -3,6 +3,11 @@
 All HIP code is compiled with packed-FP32 instruction selection disabled
 (``-Xclang -target-feature -Xclang -packed-fp32-ops``); the host pass warns
 that it does not know the feature, which is harmless.
+
+``-ffp-contract=on`` fuses a*b+c only inside one source expression, so the
+rounding of every operation is fixed by the source and not by how a kernel
+inlines, peels or unrolls it: the batched-sweep kernel and the single-case
+kernel, which share the per-node code, then round identically.
 """
 import os
 import subprocess
@@ -18,6 +23,7 @@ ARCH = os.environ.get("PMLBM_ARCH", "gfx950")
 
 def build(verbose: bool = False) -> str:
     cmd = ["/opt/rocm/bin/hipcc", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
+           "-ffp-contract=on",
            "-shared", "-Wall", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-I", os.path.join(ROOT, "include"), "-I", CSRC,
            "-o", LIB + ".tmp"] + [os.path.join(CSRC, s) for s in SOURCES]

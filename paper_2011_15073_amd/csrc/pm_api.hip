@@ -11,7 +11,10 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <algorithm>
+#include <climits>
 #include <type_traits>
+#include <vector>
 
 #include "pm_internal.h"
 
@@ -552,6 +555,399 @@ int pm_copy_probe(const void* src, void* dst, size_t bytes, void* hip_stream) {
   }
   return PM_OK;
 }
+
+// ---------------------------------------------------------------------------
+// Batched parameter sweep
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+struct pm_sweep {
+  int ncases;
+  int dtype;
+  int order;
+  hipStream_t stream;
+  hipStream_t cap_stream;
+  std::vector<pm_ctx*> ctx;
+  std::vector<int> ntiles, tile_base;
+  int total_tiles;
+  void* d_cases;        // SweepCase<T>[ncases]
+  int2* d_sched;        // schedule entries (case, tile)
+  int* d_live;          // 1 while the case still runs
+  pm::SweepStatus* d_st;
+  double* d_partial;    // per-tile residual partials, case-major
+  std::vector<unsigned char> h_cases;  // host copy of the case table (kept for the async copy)
+  std::vector<int2> h_sched;
+  std::vector<int> h_live;
+  std::vector<pm::SweepStatus> h_st;
+  int64_t gsteps;       // steps taken by the cases still live
+  int64_t graph_chunk;  // steps in the captured chunk
+  double graph_tol;
+  int64_t graph_max;
+  hipGraphExec_t graph[2];
+  char err[512];
+};
+
+namespace {
+
+constexpr size_t SWEEP_ALIGN = size_t(1) << 21;
+
+size_t align_to(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+struct SweepLayout {
+  std::vector<size_t> off, bytes;
+  size_t off_cases, off_sched, off_live, off_st, off_partial, total;
+  int total_tiles;
+};
+
+int sweep_layout(const pm_params* cases, int n, SweepLayout& L, char* msg, size_t len) {
+  if (!cases || n <= 0 || n > 4096) {
+    snprintf(msg, len, "sweep: need 1..4096 cases");
+    return PM_EINVAL;
+  }
+  L.off.resize(n);
+  L.bytes.resize(n);
+  size_t o = 0;
+  int tiles = 0;
+  for (int i = 0; i < n; ++i) {
+    pm_lattice lat;
+    int rc = map_params(cases[i], lat, msg, len);
+    if (rc) return rc;
+    if (cases[i].dtype != cases[0].dtype) {
+      snprintf(msg, len, "sweep: all cases must share one dtype");
+      return PM_EINVAL;
+    }
+    if (cases[i].has_logda) {
+      snprintf(msg, len, "sweep: per-cell log-Da planes are not supported in a sweep");
+      return PM_EINVAL;
+    }
+    L.off[i] = o;
+    L.bytes[i] = layout_of(cases[i]).total;
+    o = align_to(o + L.bytes[i], SWEEP_ALIGN);
+    tiles += ((cases[i].nx + pm::TILE - 1) / pm::TILE) * cases[i].ny;
+  }
+  const size_t case_sz = cases[0].dtype == PM_FP64 ? sizeof(pm::SweepCase<double>) : sizeof(pm::SweepCase<float>);
+  L.off_cases = o;
+  o = align_up(o + n * case_sz);
+  L.off_sched = o;
+  o = align_up(o + (size_t)tiles * sizeof(int2));
+  L.off_live = o;
+  o = align_up(o + n * sizeof(int));
+  L.off_st = o;
+  o = align_up(o + n * sizeof(pm::SweepStatus));
+  L.off_partial = o;
+  o = align_up(o + (size_t)tiles * sizeof(double));
+  L.total = o;
+  L.total_tiles = tiles;
+  return PM_OK;
+}
+
+int sweep_fail(pm_sweep* s, int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(s ? s->err : g_last_err, 512, fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+void build_schedule(pm_sweep* s) {
+  const int n = s->ncases;
+  std::vector<int> ids(n);
+  for (int i = 0; i < n; ++i) ids[i] = i;
+  if (s->order == PM_ORDER_LARGEST)
+    std::stable_sort(ids.begin(), ids.end(), [&](int a, int b) { return s->ntiles[a] > s->ntiles[b]; });
+  s->h_sched.clear();
+  s->h_sched.reserve(s->total_tiles);
+  if (s->order == PM_ORDER_INTERLEAVE) {
+    int maxt = 0;
+    for (int i = 0; i < n; ++i) maxt = std::max(maxt, s->ntiles[i]);
+    for (int t = 0; t < maxt; ++t)
+      for (int i = 0; i < n; ++i)
+        if (t < s->ntiles[i]) s->h_sched.push_back(make_int2(i, t));
+  } else {
+    for (int i : ids)
+      for (int t = 0; t < s->ntiles[i]; ++t) s->h_sched.push_back(make_int2(i, t));
+  }
+}
+
+hipError_t sweep_enqueue_chunk(pm_sweep* s, hipStream_t st, int64_t chunk, int parity0, double tol,
+                               int64_t max_steps) {
+  hipError_t e = hipSuccess;
+  for (int64_t t = 0; t < chunk && e == hipSuccess; ++t) {
+    const int par = (int)((parity0 + t) & 1);
+    if (s->dtype == PM_FP64)
+      e = pm::launch_step_multi<double>((const pm::SweepCase<double>*)s->d_cases, s->d_sched, s->d_live,
+                                        s->total_tiles, par, st);
+    else
+      e = pm::launch_step_multi<float>((const pm::SweepCase<float>*)s->d_cases, s->d_sched, s->d_live,
+                                       s->total_tiles, par, st);
+  }
+  if (e != hipSuccess) return e;
+  const int par_end = (int)((parity0 + chunk) & 1);
+  if (s->dtype == PM_FP64)
+    return pm::launch_resid_multi<double>((const pm::SweepCase<double>*)s->d_cases, s->ncases, s->d_sched,
+                                          s->d_live, s->total_tiles, par_end, s->d_partial, s->d_st, chunk,
+                                          tol, max_steps, st);
+  return pm::launch_resid_multi<float>((const pm::SweepCase<float>*)s->d_cases, s->ncases, s->d_sched,
+                                       s->d_live, s->total_tiles, par_end, s->d_partial, s->d_st, chunk, tol,
+                                       max_steps, st);
+}
+
+void sweep_drop_graphs(pm_sweep* s) {
+  for (auto& g : s->graph)
+    if (g) {
+      (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+}
+
+int sweep_graph(pm_sweep* s, int parity, int64_t chunk, double tol, int64_t max_steps) {
+  if (s->graph_chunk != chunk || s->graph_tol != tol || s->graph_max != max_steps) {
+    sweep_drop_graphs(s);
+    s->graph_chunk = chunk;
+    s->graph_tol = tol;
+    s->graph_max = max_steps;
+  }
+  if (s->graph[parity]) return PM_OK;
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return sweep_fail(s, PM_EDEVICE, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+  hipError_t le = sweep_enqueue_chunk(s, s->cap_stream, chunk, parity, tol, max_steps);
+  e = hipStreamEndCapture(s->cap_stream, &g);
+  if (le != hipSuccess || e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return sweep_fail(s, PM_EDEVICE, "capturing the sweep chunk: %s",
+                      hipGetErrorString(le != hipSuccess ? le : e));
+  }
+  e = hipGraphInstantiate(&s->graph[parity], g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    s->graph[parity] = nullptr;
+    return sweep_fail(s, PM_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  }
+  return PM_OK;
+}
+
+template <typename T> const pm::KParams<T>& kparams_of(const pm_ctx* c);
+template <> const pm::KParams<float>& kparams_of<float>(const pm_ctx* c) { return c->k32; }
+template <> const pm::KParams<double>& kparams_of<double>(const pm_ctx* c) { return c->k64; }
+
+template <typename T>
+void fill_case(pm_sweep* s, int i, pm_ctx* c) {
+  pm::SweepCase<T> sc{};
+  sc.p = kparams_of<T>(c);
+  sc.snap = (T*)((char*)c->ws + c->lay.off_snap);
+  sc.tiles_x = c->launch.tiles_x;
+  sc.ntiles = c->launch.ntiles;
+  sc.tile_base = s->tile_base[i];
+  sc.pow = c->pow ? 1 : 0;
+  memcpy(s->h_cases.data() + i * sizeof(sc), &sc, sizeof(sc));
+}
+
+}  // namespace
+
+extern "C" {
+
+int pm_sweep_workspace_bytes(const pm_params* cases, int ncases, size_t* bytes) {
+  if (!bytes) return PM_EINVAL;
+  SweepLayout L;
+  char msg[256];
+  int rc = sweep_layout(cases, ncases, L, msg, sizeof msg);
+  if (rc) {
+    set_global_err("%s", msg);
+    return rc;
+  }
+  *bytes = L.total;
+  return PM_OK;
+}
+
+int pm_sweep_create(const pm_params* cases, int ncases, void* dev_ws, size_t ws_bytes, void* hip_stream,
+                    pm_sweep** out) {
+  if (!out) return PM_EINVAL;
+  *out = nullptr;
+  SweepLayout L;
+  char msg[256];
+  int rc = sweep_layout(cases, ncases, L, msg, sizeof msg);
+  if (rc) {
+    set_global_err("%s", msg);
+    return rc;
+  }
+  if (!dev_ws || ws_bytes < L.total) {
+    set_global_err("pm_sweep_create: workspace of %zu bytes is smaller than the %zu needed", ws_bytes, L.total);
+    return PM_ESTATE;
+  }
+  if (((uintptr_t)dev_ws) % ALIGN) {
+    set_global_err("pm_sweep_create: workspace must be %zu-byte aligned", ALIGN);
+    return PM_EINVAL;
+  }
+  pm_sweep* s = new (std::nothrow) pm_sweep();
+  if (!s) return PM_EDEVICE;
+  s->ncases = ncases;
+  s->dtype = cases[0].dtype;
+  s->order = PM_ORDER_CASE;
+  s->stream = (hipStream_t)hip_stream;
+  s->total_tiles = L.total_tiles;
+  char* base = (char*)dev_ws;
+  s->d_cases = base + L.off_cases;
+  s->d_sched = (int2*)(base + L.off_sched);
+  s->d_live = (int*)(base + L.off_live);
+  s->d_st = (pm::SweepStatus*)(base + L.off_st);
+  s->d_partial = (double*)(base + L.off_partial);
+  s->graph_chunk = -1;
+  s->ctx.assign(ncases, nullptr);
+  s->ntiles.resize(ncases);
+  s->tile_base.resize(ncases);
+  const size_t case_sz = s->dtype == PM_FP64 ? sizeof(pm::SweepCase<double>) : sizeof(pm::SweepCase<float>);
+  s->h_cases.assign(ncases * case_sz, 0);
+  int tb = 0;
+  for (int i = 0; i < ncases; ++i) {
+    rc = pm_init(&cases[i], base + L.off[i], L.bytes[i], hip_stream, &s->ctx[i]);
+    if (rc) {
+      snprintf(s->err, sizeof s->err, "case %d: %s", i, g_last_err);
+      set_global_err("%s", s->err);
+      pm_sweep_destroy(s);
+      return rc;
+    }
+    s->ntiles[i] = s->ctx[i]->launch.ntiles;
+    s->tile_base[i] = tb;
+    tb += s->ntiles[i];
+    if (s->dtype == PM_FP64) fill_case<double>(s, i, s->ctx[i]);
+    else fill_case<float>(s, i, s->ctx[i]);
+  }
+  build_schedule(s);
+  s->h_live.assign(ncases, 1);
+  s->h_st.assign(ncases, pm::SweepStatus{0, INFINITY});
+  hipError_t e = hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(s->d_cases, s->h_cases.data(), s->h_cases.size(), hipMemcpyHostToDevice, s->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(s->d_sched, s->h_sched.data(), s->h_sched.size() * sizeof(int2), hipMemcpyHostToDevice,
+                       s->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(s->d_live, s->h_live.data(), ncases * sizeof(int), hipMemcpyHostToDevice, s->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(s->d_st, s->h_st.data(), ncases * sizeof(pm::SweepStatus), hipMemcpyHostToDevice,
+                       s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) {
+    set_global_err("pm_sweep_create: %s", hipGetErrorString(e));
+    pm_sweep_destroy(s);
+    return PM_EDEVICE;
+  }
+  *out = s;
+  return PM_OK;
+}
+
+int pm_sweep_set_order(pm_sweep* s, int order) {
+  if (!s) return PM_EINVAL;
+  if (order < PM_ORDER_CASE || order > PM_ORDER_INTERLEAVE)
+    return sweep_fail(s, PM_EINVAL, "pm_sweep_set_order: unknown order %d", order);
+  s->order = order;
+  build_schedule(s);
+  sweep_drop_graphs(s);
+  hipError_t e = hipMemcpyAsync(s->d_sched, s->h_sched.data(), s->h_sched.size() * sizeof(int2),
+                                hipMemcpyHostToDevice, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return sweep_fail(s, PM_EDEVICE, "pm_sweep_set_order: %s", hipGetErrorString(e));
+  return PM_OK;
+}
+
+int pm_sweep_advance(pm_sweep* s, double tol, int64_t check_every, int64_t max_steps, int64_t max_chunks,
+                     int* nlive) {
+  if (!s) return PM_EINVAL;
+  if (check_every <= 0 || max_steps < 0 || max_chunks <= 0)
+    return sweep_fail(s, PM_EINVAL, "pm_sweep_advance: bad chunk, cap or chunk budget");
+  hipError_t e = hipSuccess;
+  int live = 0;
+  for (int64_t chunk = 0;; ++chunk) {
+    live = 0;
+    for (int i = 0; i < s->ncases; ++i) live += s->h_live[i];
+    if (!live || chunk >= max_chunks) break;
+    const int parity = (int)(s->gsteps & 1);
+    int rc = sweep_graph(s, parity, check_every, tol, max_steps);
+    if (rc) return rc;
+    e = hipGraphLaunch(s->graph[parity], s->stream);
+    if (e != hipSuccess) return sweep_fail(s, PM_EDEVICE, "hipGraphLaunch: %s", hipGetErrorString(e));
+    s->gsteps += check_every;
+    e = hipMemcpyAsync(s->h_live.data(), s->d_live, s->ncases * sizeof(int), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return sweep_fail(s, PM_EDEVICE, "pm_sweep_advance: %s", hipGetErrorString(e));
+  }
+  e = hipMemcpyAsync(s->h_st.data(), s->d_st, s->ncases * sizeof(pm::SweepStatus), hipMemcpyDeviceToHost,
+                     s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return sweep_fail(s, PM_EDEVICE, "pm_sweep_advance: %s", hipGetErrorString(e));
+  for (int i = 0; i < s->ncases; ++i) s->ctx[i]->steps = s->h_st[i].steps;
+  if (nlive) *nlive = live;
+  return PM_OK;
+}
+
+int pm_sweep_run(pm_sweep* s, double tol, int64_t check_every, int64_t max_steps, int64_t* steps_out,
+                 double* r_out) {
+  int live = 1;
+  while (live) {
+    int rc = pm_sweep_advance(s, tol, check_every, max_steps, INT64_MAX, &live);
+    if (rc) return rc;
+  }
+  return pm_sweep_status(s, steps_out, r_out);
+}
+
+int pm_sweep_status(const pm_sweep* s, int64_t* steps_out, double* r_out) {
+  if (!s) return PM_EINVAL;
+  int rc = PM_OK;
+  for (int i = 0; i < s->ncases; ++i) {
+    if (steps_out) steps_out[i] = s->h_st[i].steps;
+    if (r_out) r_out[i] = s->h_st[i].residual;
+    if (!(s->h_st[i].residual <= 1.7976931348623157e308) && !s->h_live[i] && s->h_st[i].steps > 0) rc = PM_EDIVERGED;
+  }
+  if (rc) sweep_fail((pm_sweep*)s, rc, "a case stopped on a NaN/Inf residual");
+  return rc;
+}
+
+int pm_sweep_step(pm_sweep* s, int64_t k) {
+  if (!s) return PM_EINVAL;
+  if (k < 0) return sweep_fail(s, PM_EINVAL, "pm_sweep_step: k must be >= 0");
+  hipError_t e = hipSuccess;
+  for (int64_t t = 0; t < k && e == hipSuccess; ++t) {
+    const int par = (int)((s->gsteps + t) & 1);
+    if (s->dtype == PM_FP64)
+      e = pm::launch_step_multi<double>((const pm::SweepCase<double>*)s->d_cases, s->d_sched, s->d_live,
+                                        s->total_tiles, par, s->stream);
+    else
+      e = pm::launch_step_multi<float>((const pm::SweepCase<float>*)s->d_cases, s->d_sched, s->d_live,
+                                       s->total_tiles, par, s->stream);
+  }
+  if (e != hipSuccess) return sweep_fail(s, PM_EDEVICE, "pm_sweep_step: %s", hipGetErrorString(e));
+  // live cases advance together; the per-case counters follow on the device
+  // only through pm_sweep_run, so keep the host copies in step here
+  s->gsteps += k;
+  for (int i = 0; i < s->ncases; ++i)
+    if (s->h_live[i]) {
+      s->ctx[i]->steps += k;
+      s->h_st[i].steps += k;
+    }
+  e = hipMemcpyAsync(s->d_st, s->h_st.data(), s->ncases * sizeof(pm::SweepStatus), hipMemcpyHostToDevice,
+                     s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return sweep_fail(s, PM_EDEVICE, "pm_sweep_step: %s", hipGetErrorString(e));
+  return PM_OK;
+}
+
+int pm_sweep_case(pm_sweep* s, int i, pm_ctx** out) {
+  if (!s || !out) return PM_EINVAL;
+  if (i < 0 || i >= s->ncases) return sweep_fail(s, PM_EINVAL, "pm_sweep_case: index %d out of range", i);
+  *out = s->ctx[i];
+  return PM_OK;
+}
+
+void pm_sweep_destroy(pm_sweep* s) {
+  if (!s) return;
+  sweep_drop_graphs(s);
+  for (pm_ctx* c : s->ctx) pm_destroy(c);
+  if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
+  delete s;
+}
+
+const char* pm_sweep_last_error(const pm_sweep* s) { return s ? s->err : g_last_err; }
 
 const char* pm_strerror(int code) {
   switch (code) {

@@ -42,6 +42,23 @@ struct KParams {
   T inv_U;         // 1 / U_lb
 };
 
+// One case of a batched sweep, as the device sees it.
+template <typename T>
+struct SweepCase {
+  KParams<T> p;
+  T* snap;       // residual snapshot of theta (shifted)
+  int tiles_x;   // row tiles per row
+  int ntiles;    // tiles of this case
+  int tile_base; // first slot of this case in the case-major per-tile arrays
+  int pow;       // n != 1: solve the power-law viscosity
+};
+
+// Per-case progress of a sweep, kept on the device.
+struct SweepStatus {
+  int64_t steps;     // steps taken by this case
+  double residual;   // last max |dT| over a chunk
+};
+
 struct Launch {
   hipStream_t stream;
   int tiles_x;     // row tiles of TILE nodes
@@ -79,6 +96,13 @@ hipError_t launch_set_pop(const KParams<T>& p, const Launch& L, const void* f, c
 template <typename T>
 hipError_t launch_set_logda(const KParams<T>& p, const Launch& L, T* dst, const void* src,
                             int in_fp64);
+template <typename T>
+hipError_t launch_step_multi(const SweepCase<T>* cases, const int2* sched, const int* live,
+                             int nsched, int parity, hipStream_t s);
+template <typename T>
+hipError_t launch_resid_multi(const SweepCase<T>* cases, int ncases, const int2* sched, int* live,
+                              int nsched, int parity, double* partial, SweepStatus* st,
+                              int64_t chunk, double tol, int64_t max_steps, hipStream_t s);
 hipError_t launch_write_header(void* dst, int64_t steps, uint64_t tag, hipStream_t s);
 hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, hipStream_t s);
 

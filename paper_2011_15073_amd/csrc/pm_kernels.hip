@@ -49,17 +49,27 @@ __device__ __forceinline__ int tile_of_block(int b, int) { return b; }
 // (v_rcp_f32, v_exp_f32, v_log_f32, v_sqrt_f32, about 1 ulp): the FP32 path is
 // held to 1e-4 against the FP64 oracle.  FP64 keeps IEEE division and the
 // library exp2 / log2 / sqrt.
+#ifndef PM_FAST_MATH
+#define PM_FAST_MATH 1
+#endif
 template <typename T> __device__ __forceinline__ T frcp(T x);
-template <> __device__ __forceinline__ float frcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
-template <> __device__ __forceinline__ double frcp<double>(double x) { return 1.0 / x; }
 template <typename T> __device__ __forceinline__ T flog2(T x);
-template <> __device__ __forceinline__ float flog2<float>(float x) { return __builtin_amdgcn_logf(x); }
-template <> __device__ __forceinline__ double flog2<double>(double x) { return log2(x); }
 template <typename T> __device__ __forceinline__ T fexp2(T x);
-template <> __device__ __forceinline__ float fexp2<float>(float x) { return __builtin_amdgcn_exp2f(x); }
-template <> __device__ __forceinline__ double fexp2<double>(double x) { return exp2(x); }
 template <typename T> __device__ __forceinline__ T fsqrt(T x);
+#if PM_FAST_MATH
+template <> __device__ __forceinline__ float frcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <> __device__ __forceinline__ float flog2<float>(float x) { return __builtin_amdgcn_logf(x); }
+template <> __device__ __forceinline__ float fexp2<float>(float x) { return __builtin_amdgcn_exp2f(x); }
 template <> __device__ __forceinline__ float fsqrt<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
+#else
+template <> __device__ __forceinline__ float frcp<float>(float x) { return 1.0f / x; }
+template <> __device__ __forceinline__ float flog2<float>(float x) { return log2f(x); }
+template <> __device__ __forceinline__ float fexp2<float>(float x) { return exp2f(x); }
+template <> __device__ __forceinline__ float fsqrt<float>(float x) { return sqrtf(x); }
+#endif
+template <> __device__ __forceinline__ double frcp<double>(double x) { return 1.0 / x; }
+template <> __device__ __forceinline__ double flog2<double>(double x) { return log2(x); }
+template <> __device__ __forceinline__ double fexp2<double>(double x) { return exp2(x); }
 template <> __device__ __forceinline__ double fsqrt<double>(double x) { return sqrt(x); }
 
 // Global loads and stores; NT = streaming (non-temporal) hint, used for the
@@ -72,6 +82,9 @@ __device__ __forceinline__ T ldg(const T* a) {
 }
 template <typename T, bool NT>
 __device__ __forceinline__ void stg(T* a, T v) {
+#ifdef PM_EMULATE_FP32_STORAGE
+  v = (T)(float)v;
+#endif
   if constexpr (NT) __builtin_nontemporal_store(v, a);
   else *a = v;
 }
@@ -443,11 +456,9 @@ __device__ __forceinline__ void collide(const KParams<T>& p, int k, T df[9], T d
   dg[4] = (c03 - c2) - c4;
 }
 
+// One row tile [i0, i0 + TILE) of row j: gather, collide, scatter.
 template <typename T, bool ODD, bool POW, bool LOGDA>
-__global__ __launch_bounds__(TILE) void k_step(KParams<T> p, int tiles_x, int ntiles) {
-  const int tile = tile_of_block(blockIdx.x, ntiles);
-  const int j = tile / tiles_x;
-  const int i0 = (tile - j * tiles_x) * TILE;
+__device__ __forceinline__ void step_tile(const KParams<T>& p, int i0, int j) {
   const int i = i0 + threadIdx.x;
   T df[9], dg[5];
   if (ODD) {
@@ -467,6 +478,31 @@ __global__ __launch_bounds__(TILE) void k_step(KParams<T> p, int tiles_x, int nt
   load_node<T, ODD>(p, i, j, df, dg);
   collide<T, POW, LOGDA>(p, j * p.nx + i, df, dg);
   store_node<T, ODD>(p, i, j, df, dg);
+}
+
+template <typename T, bool ODD, bool POW, bool LOGDA>
+__global__ __launch_bounds__(TILE) void k_step(KParams<T> p, int tiles_x, int ntiles) {
+  const int tile = tile_of_block(blockIdx.x, ntiles);
+  const int j = tile / tiles_x;
+  step_tile<T, ODD, POW, LOGDA>(p, (tile - j * tiles_x) * TILE, j);
+}
+
+// ---- batched parameter sweep: one launch steps every live case ----
+// Workgroup b takes the (case, tile) pair of entry b of the schedule; cases
+// that have met their stopping test are skipped.  Each case runs the same
+// tile body as the single-case kernel, so a case advanced here is bitwise
+// identical to the same case advanced alone.
+template <typename T, bool ODD>
+__global__ __launch_bounds__(TILE) void k_step_multi(const SweepCase<T>* __restrict__ cases,
+                                                     const int2* __restrict__ sched,
+                                                     const int* __restrict__ live) {
+  const int2 e = sched[blockIdx.x];  // (case, tile within the case)
+  if (!live[e.x]) return;
+  const SweepCase<T>& c = cases[e.x];
+  const int j = e.y / c.tiles_x;
+  const int i0 = (e.y - j * c.tiles_x) * TILE;
+  if (c.pow) step_tile<T, ODD, true, false>(c.p, i0, j);
+  else step_tile<T, ODD, false, false>(c.p, i0, j);
 }
 
 // Rest state: df = 0, dg_q = w_q (T_init - T_ref).
@@ -553,6 +589,66 @@ __global__ __launch_bounds__(256) void k_max_final(const double* partial, int n,
     __syncthreads();
   }
   if (threadIdx.x == 0) out[0] = red[0];
+}
+
+// Sweep residual: one workgroup per schedule entry (a row tile of a live
+// case) -> max |theta - snapshot| over the tile into the tile's slot of the
+// case-major partial array, snapshot := theta.
+template <typename T>
+__global__ __launch_bounds__(TILE) void k_resid_multi(const SweepCase<T>* __restrict__ cases,
+                                                      const int2* __restrict__ sched,
+                                                      const int* __restrict__ live, int parity,
+                                                      double* __restrict__ partial) {
+  __shared__ double red[TILE];
+  const int2 e = sched[blockIdx.x];
+  if (!live[e.x]) return;  // uniform over the workgroup
+  const SweepCase<T>& c = cases[e.x];
+  const int j = e.y / c.tiles_x;
+  const int i = (e.y - j * c.tiles_x) * TILE + threadIdx.x;
+  double mx = 0.0;
+  if (i < c.p.nx) {
+    T g[5];
+    if (parity) load_g<T, true>(c.p, i, j, g); else load_g<T, false>(c.p, i, j, g);
+    const T dT = g[0] + ((g[1] + g[2]) + (g[3] + g[4]));
+    const int64_t k = (int64_t)j * c.p.nx + i;
+    double d = fabs((double)dT - (double)c.snap[k]);
+    if (!(d <= 1.7976931348623157e308)) d = INFINITY;  // NaN / Inf -> +Inf
+    mx = d;
+    c.snap[k] = dT;
+  }
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int s = TILE / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      const double o = red[threadIdx.x + s];
+      red[threadIdx.x] = o > red[threadIdx.x] ? o : red[threadIdx.x];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[c.tile_base + e.y] = red[0];
+}
+
+// Stopping test of every live case after a chunk of steps: r = max over the
+// case's tiles; the case stops when r < tol, when r is not finite, or when
+// it has reached max_steps.  One workgroup, one thread per case.
+template <typename T>
+__global__ void k_retire(const SweepCase<T>* __restrict__ cases, int ncases,
+                         const double* __restrict__ partial, int* __restrict__ live,
+                         SweepStatus* __restrict__ st, int64_t chunk, double tol,
+                         int64_t max_steps) {
+  for (int c = threadIdx.x; c < ncases; c += blockDim.x) {
+    if (!live[c]) continue;
+    const SweepCase<T>& cs = cases[c];
+    double r = 0.0;
+    for (int b = 0; b < cs.ntiles; ++b) {
+      const double v = partial[cs.tile_base + b];
+      r = v > r ? v : r;
+    }
+    st[c].steps += chunk;
+    st[c].residual = r;
+    const bool finite = r <= 1.7976931348623157e308;
+    if (r < tol || !finite || st[c].steps >= max_steps) live[c] = 0;
+  }
 }
 
 template <typename T, bool ODD, bool POW, bool LOGDA, typename O>
@@ -654,6 +750,27 @@ hipError_t launch_step(const KParams<T>& p, const Launch& L, int parity, bool po
     else { if (logda) PM_STEP(false, false, true); else PM_STEP(false, false, false); }
   }
 #undef PM_STEP
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_step_multi(const SweepCase<T>* cases, const int2* sched, const int* live,
+                             int nsched, int parity, hipStream_t s) {
+  if (parity)
+    hipLaunchKernelGGL((k_step_multi<T, true>), dim3(nsched), dim3(TILE), 0, s, cases, sched, live);
+  else
+    hipLaunchKernelGGL((k_step_multi<T, false>), dim3(nsched), dim3(TILE), 0, s, cases, sched, live);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_resid_multi(const SweepCase<T>* cases, int ncases, const int2* sched, int* live,
+                              int nsched, int parity, double* partial, SweepStatus* st,
+                              int64_t chunk, double tol, int64_t max_steps, hipStream_t s) {
+  hipLaunchKernelGGL((k_resid_multi<T>), dim3(nsched), dim3(TILE), 0, s, cases, sched,
+                     (const int*)live, parity, partial);
+  hipLaunchKernelGGL((k_retire<T>), dim3(1), dim3(64), 0, s, cases, ncases, (const double*)partial,
+                     live, st, chunk, tol, max_steps);
   return hipGetLastError();
 }
 
@@ -761,7 +878,12 @@ hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, hipStream
   template hipError_t launch_get_pop<T>(const KParams<T>&, const Launch&, int, void*, void*, int); \
   template hipError_t launch_set_pop<T>(const KParams<T>&, const Launch&, const void*,          \
                                         const void*, int);                                      \
-  template hipError_t launch_set_logda<T>(const KParams<T>&, const Launch&, T*, const void*, int);
+  template hipError_t launch_set_logda<T>(const KParams<T>&, const Launch&, T*, const void*, int); \
+  template hipError_t launch_step_multi<T>(const SweepCase<T>*, const int2*, const int*, int, int, \
+                                           hipStream_t);                                          \
+  template hipError_t launch_resid_multi<T>(const SweepCase<T>*, int, const int2*, int*, int, int, \
+                                            double*, SweepStatus*, int64_t, double, int64_t,      \
+                                            hipStream_t);
 PM_INST(float)
 PM_INST(double)
 #undef PM_INST

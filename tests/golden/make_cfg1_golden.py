@@ -1,0 +1,43 @@
+"""Writes tests/golden/cfg1_256_oracle.npz with the FP64 oracle only.
+
+Workload: 256 x 256 porous cavity, modified power law n = 0.6 with the
+viscosity clamped to [0.1, 10] nu0, Da = 1e-3, Ra = 1e5, Pr = 10, eps = 0.6,
+from rest, run until max |dT| over 1000 steps < 1e-8 (checked every 1000
+steps).  Stored: the stopping step S*, the final residual, the hot-wall
+Nusselt number (Eq. 24), max |U|, max |V| over the whole field, the
+nondimensional fields U, V, theta on every 4th node in each direction, and
+U, V, theta on the two hot-wall columns.
+
+Run from the repository root:  python tests/golden/make_cfg1_golden.py
+(about an hour on 8 cores).
+"""
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+import oracle as O  # noqa: E402
+
+PHYS = dict(n=0.6, Da=1e-3, Ra=1e5, Pr=10.0, eps=0.6, nu_lo=0.1, nu_hi=10.0)
+N = 256
+
+
+def main():
+    t0 = time.time()
+    orc = O.Oracle.from_physics(O.physics(N, **PHYS))
+    r, steps = orc.run_to_steady(tol=1e-8, check_every=1000, max_steps=2_000_000)
+    U, V, th = orc.fields()
+    out = os.path.join(ROOT, "tests", "golden", "cfg1_256_oracle.npz")
+    np.savez_compressed(out, steps=steps, residual=r, nu_bar=orc.nu_bar(),
+                        maxU=np.abs(U).max(), maxV=np.abs(V).max(), maxT=np.abs(th).max(),
+                        U4=U[::4, ::4], V4=V[::4, ::4], T4=th[::4, ::4],
+                        Uw=U[:, :2], Vw=V[:, :2], Tw=th[:, :2],
+                        phys=np.array(str(PHYS)))
+    print(f"S* = {steps}, r = {r:.3e}, Nu = {orc.nu_bar():.12f}, {time.time() - t0:.0f} s -> {out}")
+
+
+if __name__ == "__main__":
+    main()
