@@ -20,6 +20,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -143,6 +144,49 @@ def sweep_main(args):
         "steps_per_case": steps}), flush=True)
 
 
+def adjoint_main(args):
+    """Cost of the gradient of Nu_bar on the 256 x 256 cavity (FP32 forward
+    state, FP64 adjoint, n = 0.7, Ra = 1e4, per-cell log10 Da ~ U[-3, -1]
+    seed 0, T = 5000 steps, checkpoints every ceil(sqrt(T)) steps): forward
+    with checkpoints vs backward (segment replay + adjoint steps).  With the
+    [0.1, 10] viscosity clamp the exact adjoint of this workload grows without
+    bound (low-shear regions amplify perturbations), so the gradient is taken
+    with the shear floor gamma* = --adjoint-shear-floor; the work per step is
+    the same either way."""
+    import torch
+    import paper_2011_15073_amd as P
+    from paper_2011_15073_amd import inputs
+
+    N, T = 256, args.adjoint_steps
+    ld = torch.from_numpy(inputs.logda_field(N, seed=0))
+    times = []
+    for rep in range(2):
+        cav = P.Cavity(N, dtype="fp32", logda=ld, n=0.7, Ra=1e4, Pr=10.0, eps=0.6)
+        adj = P.Adjoint(cav, T, shear_floor=args.adjoint_shear_floor)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        J = adj.forward()
+        t1 = time.perf_counter()
+        gld, gn, gRa = adj.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        times.append((t1 - t0, t2 - t1))
+        log(f"adjoint: rep {rep}: forward {t1 - t0:.3f} s, backward {t2 - t1:.3f} s, J {J:.8f}")
+        adj.close()
+        del adj, cav
+    fwd, bwd = times[-1]
+    print(json.dumps({
+        "metric": "adjoint/forward cost", "value": round(bwd / fwd, 3), "unit": "x",
+        "n_gpus": 1, "higher_is_better": False, "dtype": "f32 forward / f64 adjoint",
+        "data": "synthetic",
+        "config": {"workload": "256x256 porous cavity, n=0.7, Ra=1e4, Pr=10, eps=0.6, per-cell "
+                               "log10 Da ~ U[-3,-1] (seed 0), J = Nu_bar after T steps",
+                   "T": T, "checkpoint_every": math.ceil(math.sqrt(T)),
+                   "shear_floor": args.adjoint_shear_floor},
+        "forward_s": round(fwd, 4), "backward_s": round(bwd, 4), "J": J,
+        "dJ_dn": gn, "dJ_dRa": gRa, "max_abs_dJ_dlogDa": float(gld.abs().max())}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -155,6 +199,11 @@ def main():
     ap.add_argument("--sweep-dtype", default="fp64", choices=["fp32", "fp64"])
     ap.add_argument("--sweep-tol", type=float, default=1e-8)
     ap.add_argument("--sweep-cap", type=int, default=3_000_000)
+    ap.add_argument("--adjoint", action="store_true",
+                    help="time the gradient of Nu (forward with checkpoints vs backward)")
+    ap.add_argument("--adjoint-steps", type=int, default=5000)
+    ap.add_argument("--adjoint-shear-floor", type=float, default=0.1,
+                    help="nondimensional shear floor of the regularised adjoint (0: exact)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -163,6 +212,9 @@ def main():
 
     if args.sweep:
         sweep_main(args)
+        return
+    if args.adjoint:
+        adjoint_main(args)
         return
 
     import torch

@@ -219,6 +219,57 @@ int pm_sweep_case(pm_sweep* s, int i, pm_ctx** out);
 void pm_sweep_destroy(pm_sweep* s);
 const char* pm_sweep_last_error(const pm_sweep* s);
 
+/* ---- Adjoint: gradients of the Nusselt number ----
+ * J = Nu_bar (Eq. 24) after T steps from the context's current state.
+ * Gradients with respect to the per-cell log10(Da) field (has_logda = 1),
+ * the power-law index n and the Rayleigh number Ra, by the discrete adjoint
+ * of the update: transposed streaming, and the reverse-mode derivative of the
+ * node update recomputed in FP64 (the viscosity of Eq. (21) differentiated
+ * through its fixed-point equation, or through the active clamp).  Memory:
+ * checkpoints of the state every C steps (C ~ sqrt(T)); each segment is
+ * replayed out of place before its adjoint steps run in reverse.  Supported:
+ * cavity walls (no periodic axes), PM_CLAMP_NU, no extra body force.  The
+ * workspace (caller-owned device memory, 256-byte aligned) holds the
+ * checkpoints, the replayed segment, two FP64 adjoint states and per-
+ * workgroup partial sums. */
+typedef struct pm_adjoint pm_adjoint;
+
+int pm_adjoint_workspace_bytes(const pm_params* p, int64_t T, int64_t C, size_t* bytes);
+/* Bind an adjoint to a context (which it borrows; keep the context alive). */
+int pm_adjoint_create(pm_ctx* ctx, int64_t T, int64_t C, void* dev_ws, size_t ws_bytes, pm_adjoint** out);
+/* Run T steps from the context's current state, checkpointing every C
+ * steps; *J_out = Nu_bar of the final state.  Synchronises. */
+int pm_adjoint_forward(pm_adjoint* a, double* J_out);
+/* Gradients of seed * J: grad_logda (device FP64 [ny][nx], overwritten; may
+ * be NULL when has_logda = 0), *grad_n, *grad_Ra (host; may be NULL).  The
+ * context's state is left at the end of the forward run.  Synchronises.
+ * PM_EDIVERGED (outputs then meaningless) when the adjoint state exceeds
+ * 1e12 |seed| max(1, nx / ny) or is not finite: the linearised update is
+ * amplifying perturbations along this trajectory (see
+ * pm_adjoint_set_shear_floor). */
+int pm_adjoint_backward(pm_adjoint* a, double seed, void* grad_logda, double* grad_n, double* grad_Ra);
+/* Regularised derivative (default 0: the exact discrete adjoint).  Where the
+ * local nondimensional shear rate gamma* (Eq. 22 times N / U) is below
+ * gamma_floor, the adjoint holds the viscosity of Eq. (21) fixed with
+ * respect to the populations (its dependence on nu0 and n is kept).  For
+ * n < 1 the power law's slope d nu / d gamma grows like gamma^(n-2) towards
+ * zero shear, and where that meets the Darcy drag the linearised update can
+ * amplify perturbations from step to step; the floor removes that channel.
+ * PM_EINVAL for a negative or non-finite value. */
+int pm_adjoint_set_shear_floor(pm_adjoint* a, double gamma_floor);
+void pm_adjoint_destroy(pm_adjoint* a);
+const char* pm_adjoint_last_error(const pm_adjoint* a);
+
+/* One adjoint step at the context's current state S_k: given lam_next =
+ * dL/dS_{k+1} (device FP64 [14][ny][nx], f planes then g planes), writes
+ * lam = dL/dS_k, adds dL/dlog10(Da) of this step into grad_logda (device
+ * FP64 [ny][nx]) and returns (dL/dn, dL/dRa) of this step in grad_scalars[2]
+ * (host).  dev_scratch: pm_adjoint_vjp_scratch_bytes(ctx) bytes of device
+ * memory.  Synchronises.  Used to check the adjoint against autograd. */
+size_t pm_adjoint_vjp_scratch_bytes(const pm_ctx* ctx);
+int pm_adjoint_vjp(pm_ctx* ctx, const void* lam_next, void* lam, void* grad_logda, void* dev_scratch,
+                   size_t scratch_bytes, double* grad_scalars);
+
 const char* pm_strerror(int code);
 const char* pm_last_error(const pm_ctx* ctx);
 

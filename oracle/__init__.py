@@ -149,8 +149,11 @@ class Oracle:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
-            lib().orc_free(h)
+        if h and _LIB is not None:
+            try:
+                _LIB.orc_free(h)
+            except Exception:
+                pass
             self._h = None
 
     def set_logda(self, logda):

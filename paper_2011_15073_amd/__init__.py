@@ -9,6 +9,7 @@ from ._lib import (PM_CLAMP_GAMMA, PM_CLAMP_NU, PM_FP32, PM_FP64, PmError, latti
                    make_params, workspace_bytes)
 from .cavity import Cavity, copy_probe
 from .sweep import Sweep, tune
+from .adjoint import Adjoint, nusselt, vjp_step
 
-__all__ = ["Cavity", "Sweep", "tune", "copy_probe", "PmError", "make_params", "lattice_of", "workspace_bytes",
+__all__ = ["Cavity", "Sweep", "tune", "Adjoint", "nusselt", "vjp_step", "copy_probe", "PmError", "make_params", "lattice_of", "workspace_bytes",
            "PM_FP32", "PM_FP64", "PM_CLAMP_NU", "PM_CLAMP_GAMMA"]

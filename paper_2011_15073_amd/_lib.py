@@ -29,6 +29,9 @@ EXPORTS = [
     "pm_sweep_workspace_bytes", "pm_sweep_create", "pm_sweep_set_order", "pm_sweep_run",
     "pm_sweep_advance", "pm_sweep_status",
     "pm_sweep_step", "pm_sweep_case", "pm_sweep_destroy", "pm_sweep_last_error",
+    "pm_adjoint_workspace_bytes", "pm_adjoint_create", "pm_adjoint_forward",
+    "pm_adjoint_backward", "pm_adjoint_set_shear_floor", "pm_adjoint_destroy", "pm_adjoint_last_error",
+    "pm_adjoint_vjp_scratch_bytes", "pm_adjoint_vjp",
     "pm_strerror", "pm_last_error",
 ]
 
@@ -101,6 +104,15 @@ def _load():
         "pm_sweep_case": ([vp, i32, P(vp)], i32),
         "pm_sweep_destroy": ([vp], None),
         "pm_sweep_last_error": ([vp], C.c_char_p),
+        "pm_adjoint_workspace_bytes": ([P(PmParams), i64, i64, P(sz)], i32),
+        "pm_adjoint_create": ([vp, i64, i64, vp, sz, P(vp)], i32),
+        "pm_adjoint_forward": ([vp, P(dbl)], i32),
+        "pm_adjoint_backward": ([vp, dbl, vp, P(dbl), P(dbl)], i32),
+        "pm_adjoint_set_shear_floor": ([vp, dbl], i32),
+        "pm_adjoint_destroy": ([vp], None),
+        "pm_adjoint_last_error": ([vp], C.c_char_p),
+        "pm_adjoint_vjp_scratch_bytes": ([vp], sz),
+        "pm_adjoint_vjp": ([vp, vp, vp, vp, vp, sz, P(dbl)], i32),
         "pm_strerror": ([i32], C.c_char_p),
         "pm_last_error": ([vp], C.c_char_p),
     }

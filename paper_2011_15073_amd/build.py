@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpmlbm.so")
-SOURCES = ["pm_kernels.hip", "pm_api.hip"]
+SOURCES = ["pm_kernels.hip", "pm_adjoint.hip", "pm_api.hip"]
 ARCH = os.environ.get("PMLBM_ARCH", "gfx950")
 
 

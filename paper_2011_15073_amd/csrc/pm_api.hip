@@ -949,6 +949,329 @@ void pm_sweep_destroy(pm_sweep* s) {
 
 const char* pm_sweep_last_error(const pm_sweep* s) { return s ? s->err : g_last_err; }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Adjoint (gradients of the Nusselt number)
+// ---------------------------------------------------------------------------
+struct pm_adjoint {
+  pm_ctx* ctx;
+  int64_t T, C, ncp, s0;
+  size_t span;          // bytes of one raw population state (f and g planes)
+  char* cp;             // ncp checkpoints
+  char* seg;            // C + 1 states of the segment being replayed
+  double* lam[2];       // adjoint state, natural layout [14][ny][nx]
+  double* partial;      // pm::ADJ_PART doubles per workgroup
+  int nblocks;
+  double J;
+  bool have_forward;
+  pm::AdjParams ap;
+  char err[512];
+};
+
+namespace {
+
+struct AdjLayout {
+  size_t span, off_cp, off_seg, off_lam0, off_lam1, off_partial, total;
+  int64_t ncp;
+  int nblocks;
+};
+
+int adj_layout(const pm_params& p, int64_t T, int64_t C, AdjLayout& A, char* msg, size_t len) {
+  pm_lattice L;
+  int rc = map_params(p, L, msg, len);
+  if (rc) return rc;
+  if (T < 1 || C < 1 || C > T) {
+    snprintf(msg, len, "adjoint: need T >= 1 and 1 <= C <= T");
+    return PM_EINVAL;
+  }
+  if (p.periodic_x || p.periodic_y) {
+    snprintf(msg, len, "adjoint: periodic axes are not supported (cavity walls only)");
+    return PM_EINVAL;
+  }
+  if (p.clamp_mode != PM_CLAMP_NU) {
+    snprintf(msg, len, "adjoint: only PM_CLAMP_NU is supported");
+    return PM_EINVAL;
+  }
+  if (p.gx != 0.0 || p.gy != 0.0) {
+    snprintf(msg, len, "adjoint: extra body forces are not supported");
+    return PM_EINVAL;
+  }
+  const Layout lay = layout_of(p);
+  const int64_t nn = (int64_t)p.nx * p.ny;
+  A.span = lay.off_g + 5 * lay.P * lay.elem;
+  A.ncp = (T + C - 1) / C;
+  A.nblocks = ((p.nx + pm::TILE - 1) / pm::TILE) * p.ny;
+  size_t o = 0;
+  A.off_cp = o;
+  o = align_up(o + A.ncp * align_up(A.span));
+  A.off_seg = o;
+  o = align_up(o + (C + 1) * align_up(A.span));
+  A.off_lam0 = o;
+  o = align_up(o + 14 * nn * sizeof(double));
+  A.off_lam1 = o;
+  o = align_up(o + 14 * nn * sizeof(double));
+  A.off_partial = o;
+  o = align_up(o + pm::ADJ_PART * (size_t)A.nblocks * sizeof(double));
+  A.total = o;
+  return PM_OK;
+}
+
+pm::AdjParams adj_params(const pm_ctx* c) {
+  pm::AdjParams a{};
+  const pm_params& p = c->p;
+  const pm_lattice& L = c->L;
+  a.nx = p.nx;
+  a.ny = p.ny;
+  a.has_logda = p.has_logda ? 1 : 0;
+  a.pow = c->pow ? 1 : 0;
+  a.eps = L.eps;
+  a.inv_eps = 1.0 / L.eps;
+  a.Feps = L.Feps;
+  a.invK = std::isinf(L.K) ? 0.0 : 1.0 / L.K;
+  a.invsK = std::sqrt(a.invK);
+  a.inv_Kscale = 1.0 / ((double)p.nx * (double)p.nx);
+  a.gbeta = L.gbeta;
+  a.dTm = L.T_m - 0.5;
+  a.gx = p.gx;
+  a.gy = p.gy;
+  a.s_e = L.s_e;
+  a.s_eps = L.s_eps;
+  a.s_q = L.s_q;
+  a.s_g = 1.0 / L.tau_g;
+  a.sT_e = L.sT_e;
+  a.sT_nu = L.sT_nu;
+  a.T_ref = 0.5;
+  a.nu0 = L.nu0;
+  a.log2nu0 = std::log2(L.nu0);
+  a.y_lo = std::log2(L.nu_min);
+  a.y_hi = std::log2(L.nu_max);
+  a.nm1 = p.n - 1.0;
+  a.inv_n = 1.0 / p.n;
+  a.log2c = std::log2(L.gamma_scale);
+  a.lc0 = a.log2nu0 + a.nm1 * a.log2c;
+  a.g2_floor = 0.0;
+  return a;
+}
+
+template <typename T>
+pm::KParams<T> slot_params(const pm_ctx* c, const pm::KParams<T>& base, char* slot) {
+  pm::KParams<T> k = base;
+  k.f = (T*)slot;
+  k.g = (T*)(slot + c->lay.off_g);
+  return k;
+}
+
+int adj_fail(pm_adjoint* a, int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(a ? a->err : g_last_err, 512, fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+// One adjoint step at a raw state (parity given), lam_next -> lam.
+hipError_t adj_step(const pm_ctx* c, const pm::AdjParams& ap, char* state, int parity, const double* lam_next,
+                    double* lam, double* g_logda, double* partial) {
+  if (c->p.dtype == PM_FP64)
+    return pm::launch_adjoint<double>(slot_params<double>(c, c->k64, state), ap, parity, lam_next, lam, g_logda,
+                                      partial, c->stream);
+  return pm::launch_adjoint<float>(slot_params<float>(c, c->k32, state), ap, parity, lam_next, lam, g_logda,
+                                   partial, c->stream);
+}
+
+// Chain rule from the per-node parameters (ln nu0, n at fixed nu0, s_g) to
+// (n, Ra): nu0 = Pr / sqrt(Ra)^(2-n) U N, alpha = U N / sqrt(Ra),
+// s_g = 1 / (3 alpha + 1/2).
+// Fixed-order host sum of the per-workgroup partials; largest |lambda|.
+void reduce_partials(const std::vector<double>& part, double sums[3], double& lam_max) {
+  sums[0] = sums[1] = sums[2] = 0.0;
+  lam_max = 0.0;
+  for (size_t b = 0; b < part.size() / pm::ADJ_PART; ++b) {
+    for (int q = 0; q < 3; ++q) sums[q] += part[pm::ADJ_PART * b + q];
+    const double m = part[pm::ADJ_PART * b + 3];
+    lam_max = (m != m) ? INFINITY : std::max(lam_max, m);
+  }
+}
+
+// Bound on |lambda| relative to the seed (whose own size is 3 nx / ny): an
+// adjoint state this large means the backward sweep is amplifying, not
+// transporting, sensitivities.
+constexpr double ADJ_LAMBDA_LIMIT = 1e12;
+
+void chain_scalars(const pm_ctx* c, const double* sums, double* d_n, double* d_Ra) {
+  const double n = c->p.n, Ra = c->p.Ra;
+  const double sg = 1.0 / c->L.tau_g, alpha = c->L.alpha;
+  if (d_n) *d_n = sums[1] + 0.5 * std::log(Ra) * sums[0];
+  if (d_Ra) *d_Ra = -(2.0 - n) / (2.0 * Ra) * sums[0] + 1.5 * sg * sg * alpha / Ra * sums[2];
+}
+
+}  // namespace
+
+extern "C" {
+
+int pm_adjoint_workspace_bytes(const pm_params* p, int64_t T, int64_t C, size_t* bytes) {
+  if (!p || !bytes) return PM_EINVAL;
+  AdjLayout A;
+  char msg[256];
+  int rc = adj_layout(*p, T, C, A, msg, sizeof msg);
+  if (rc) {
+    set_global_err("%s", msg);
+    return rc;
+  }
+  *bytes = A.total;
+  return PM_OK;
+}
+
+int pm_adjoint_create(pm_ctx* c, int64_t T, int64_t C, void* dev_ws, size_t ws_bytes, pm_adjoint** out) {
+  if (!c || !out) return PM_EINVAL;
+  *out = nullptr;
+  AdjLayout A;
+  char msg[256];
+  int rc = adj_layout(c->p, T, C, A, msg, sizeof msg);
+  if (rc) {
+    set_global_err("%s", msg);
+    return rc;
+  }
+  if (!dev_ws || ws_bytes < A.total || ((uintptr_t)dev_ws) % ALIGN) {
+    set_global_err("pm_adjoint_create: workspace must be %zu-byte aligned and >= %zu bytes", ALIGN, A.total);
+    return PM_ESTATE;
+  }
+  pm_adjoint* a = new (std::nothrow) pm_adjoint();
+  if (!a) return PM_EDEVICE;
+  a->ctx = c;
+  a->T = T;
+  a->C = C;
+  a->ncp = A.ncp;
+  a->span = A.span;
+  char* b = (char*)dev_ws;
+  a->cp = b + A.off_cp;
+  a->seg = b + A.off_seg;
+  a->lam[0] = (double*)(b + A.off_lam0);
+  a->lam[1] = (double*)(b + A.off_lam1);
+  a->partial = (double*)(b + A.off_partial);
+  a->nblocks = A.nblocks;
+  a->ap = adj_params(c);
+  *out = a;
+  return PM_OK;
+}
+
+int pm_adjoint_forward(pm_adjoint* a, double* J_out) {
+  if (!a) return PM_EINVAL;
+  pm_ctx* c = a->ctx;
+  a->s0 = c->steps;
+  const size_t stride = align_up(a->span);
+  for (int64_t k = 0; k < a->ncp; ++k) {
+    hipError_t e = hipMemcpyAsync(a->cp + k * stride, (char*)c->ws + c->lay.off_f, a->span,
+                                  hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) return adj_fail(a, PM_EDEVICE, "checkpoint copy: %s", hipGetErrorString(e));
+    const int64_t n = std::min(a->C, a->T - k * a->C);
+    int rc = pm_step(c, n);
+    if (rc) return adj_fail(a, rc, "forward: %s", c->err);
+  }
+  int rc = pm_nu(c, &a->J);
+  if (rc) return adj_fail(a, rc, "forward: %s", c->err);
+  a->have_forward = true;
+  if (J_out) *J_out = a->J;
+  return PM_OK;
+}
+
+int pm_adjoint_backward(pm_adjoint* a, double seed, void* grad_logda, double* grad_n, double* grad_Ra) {
+  if (!a) return PM_EINVAL;
+  if (!a->have_forward) return adj_fail(a, PM_ESTATE, "pm_adjoint_backward: run pm_adjoint_forward first");
+  pm_ctx* c = a->ctx;
+  if (c->p.has_logda && !grad_logda) return adj_fail(a, PM_EINVAL, "pm_adjoint_backward: grad_logda needed");
+  const int64_t nn = (int64_t)c->p.nx * c->p.ny;
+  hipError_t e = hipMemsetAsync(a->partial, 0, pm::ADJ_PART * (size_t)a->nblocks * sizeof(double), c->stream);
+  if (e == hipSuccess && grad_logda) e = hipMemsetAsync(grad_logda, 0, nn * sizeof(double), c->stream);
+  if (e == hipSuccess) e = pm::launch_adjoint_seed(c->p.nx, c->p.ny, seed, a->lam[0], c->stream);
+  if (e != hipSuccess) return adj_fail(a, PM_EDEVICE, "backward setup: %s", hipGetErrorString(e));
+  const size_t stride = align_up(a->span);
+  const bool logda = c->p.has_logda != 0;
+  int cur = 0;
+  for (int64_t k = a->ncp - 1; k >= 0; --k) {
+    const int64_t start = k * a->C;
+    const int64_t n = std::min(a->C, a->T - start);
+    // replay the segment out of place: slot t holds S_{start + t}
+    e = hipMemcpyAsync(a->seg, a->cp + k * stride, a->span, hipMemcpyDeviceToDevice, c->stream);
+    for (int64_t t = 0; t < n && e == hipSuccess; ++t) {
+      const int parity = (int)((a->s0 + start + t) & 1);
+      char* src = a->seg + t * stride;
+      char* dst = a->seg + (t + 1) * stride;
+      if (c->p.dtype == PM_FP64)
+        e = pm::launch_step_oop(slot_params<double>(c, c->k64, src), slot_params<double>(c, c->k64, dst),
+                                c->launch, parity, c->pow, logda);
+      else
+        e = pm::launch_step_oop(slot_params<float>(c, c->k32, src), slot_params<float>(c, c->k32, dst),
+                                c->launch, parity, c->pow, logda);
+    }
+    // adjoint steps in reverse over the segment
+    for (int64_t t = n - 1; t >= 0 && e == hipSuccess; --t) {
+      const int parity = (int)((a->s0 + start + t) & 1);
+      e = adj_step(c, a->ap, a->seg + t * stride, parity, a->lam[cur], a->lam[cur ^ 1], (double*)grad_logda,
+                   a->partial);
+      cur ^= 1;
+    }
+    if (e != hipSuccess) return adj_fail(a, PM_EDEVICE, "backward: %s", hipGetErrorString(e));
+  }
+  std::vector<double> part(pm::ADJ_PART * (size_t)a->nblocks);
+  e = hipMemcpyAsync(part.data(), a->partial, part.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return adj_fail(a, PM_EDEVICE, "backward: %s", hipGetErrorString(e));
+  double sums[3], lam_max;
+  reduce_partials(part, sums, lam_max);
+  chain_scalars(c, sums, grad_n, grad_Ra);
+  const double limit = ADJ_LAMBDA_LIMIT * std::fabs(seed) * std::max(1.0, (double)c->p.nx / c->p.ny);
+  if (!(lam_max <= limit) || !std::isfinite(sums[0]) || !std::isfinite(sums[1]) || !std::isfinite(sums[2]))
+    return adj_fail(a, PM_EDIVERGED,
+                    "pm_adjoint_backward: the adjoint state grew to %.3g (limit %.3g): the linearised update "
+                    "amplifies perturbations on this trajectory (for n < 1, where low shear meets the Darcy "
+                    "drag); pm_adjoint_set_shear_floor gives a regularised gradient",
+                    lam_max, limit);
+  return PM_OK;
+}
+
+int pm_adjoint_set_shear_floor(pm_adjoint* a, double gamma_floor) {
+  if (!a) return PM_EINVAL;
+  if (!(gamma_floor >= 0.0) || std::isinf(gamma_floor))
+    return adj_fail(a, PM_EINVAL, "pm_adjoint_set_shear_floor: need a finite gamma_floor >= 0");
+  const double g = gamma_floor / a->ctx->L.gamma_scale;  // nondimensional -> lattice
+  a->ap.g2_floor = g * g;
+  return PM_OK;
+}
+
+void pm_adjoint_destroy(pm_adjoint* a) { delete a; }
+
+const char* pm_adjoint_last_error(const pm_adjoint* a) { return a ? a->err : g_last_err; }
+
+size_t pm_adjoint_vjp_scratch_bytes(const pm_ctx* c) {
+  if (!c) return 0;
+  return pm::ADJ_PART * (size_t)c->launch.ntiles * sizeof(double);
+}
+
+int pm_adjoint_vjp(pm_ctx* c, const void* lam_next, void* lam, void* grad_logda, void* dev_scratch,
+                   size_t scratch_bytes, double* grad_scalars) {
+  if (!c || !lam_next || !lam || !dev_scratch) return PM_EINVAL;
+  if (c->p.periodic_x || c->p.periodic_y || c->p.clamp_mode != PM_CLAMP_NU || c->p.gx != 0.0 || c->p.gy != 0.0)
+    return ctx_fail(c, PM_EINVAL, "pm_adjoint_vjp: cavity walls, PM_CLAMP_NU and no body force only");
+  if (c->p.has_logda && !grad_logda) return ctx_fail(c, PM_EINVAL, "pm_adjoint_vjp: grad_logda needed");
+  const size_t need = pm_adjoint_vjp_scratch_bytes(c);
+  if (scratch_bytes < need) return ctx_fail(c, PM_ESTATE, "pm_adjoint_vjp: scratch < %zu bytes", need);
+  hipError_t e = hipMemsetAsync(dev_scratch, 0, need, c->stream);
+  if (e == hipSuccess)
+    e = adj_step(c, adj_params(c), (char*)c->ws + c->lay.off_f, (int)(c->steps & 1), (const double*)lam_next,
+                 (double*)lam, (double*)grad_logda, (double*)dev_scratch);
+  std::vector<double> part(need / sizeof(double));
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(part.data(), dev_scratch, need, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return check_hip(c, e, "pm_adjoint_vjp");
+  double sums[3], lam_max;
+  reduce_partials(part, sums, lam_max);
+  if (grad_scalars) chain_scalars(c, sums, &grad_scalars[0], &grad_scalars[1]);
+  return PM_OK;
+}
+
 const char* pm_strerror(int code) {
   switch (code) {
     case PM_OK: return "ok";

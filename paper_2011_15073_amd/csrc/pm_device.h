@@ -1,0 +1,467 @@
+// pm_device.h -- device-side building blocks of the gfx950 lattice Boltzmann
+// update shared by the forward, sweep and adjoint kernels: population
+// addressing (AA pattern), the local viscosity solve, the node update.
+#pragma once
+
+#include "pm_internal.h"
+
+#include <cmath>
+
+namespace pm {
+namespace dev {
+
+
+// D2Q9 velocities, Eq. (14): 0 rest; 1-4 E, N, W, S; 5-8 NE, NW, SW, SE.
+// D2Q5 (Eq. 19) uses the first five.
+constexpr int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+constexpr int EXv[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+constexpr int EYv[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+
+// Workgroup b handles row tile b in row-major order.  Dispatch deals
+// consecutive workgroups round-robin to the 8 XCDs, so at any moment all XCDs
+// stream through one narrow band of each plane; that keeps the HBM accesses
+// of the whole chip within few DRAM pages.  (Giving each XCD its own
+// contiguous band of rows measured 5% slower at 4096^2: eight bands far apart
+// in every plane.)
+__device__ __forceinline__ int tile_of_block(int b, int) { return b; }
+
+// Arithmetic helpers.  FP32 uses the hardware approximations directly
+// (v_rcp_f32, v_exp_f32, v_log_f32, v_sqrt_f32, about 1 ulp): the FP32 path is
+// held to 1e-4 against the FP64 oracle.  FP64 keeps IEEE division and the
+// library exp2 / log2 / sqrt.
+#ifndef PM_FAST_MATH
+#define PM_FAST_MATH 1
+#endif
+template <typename T> __device__ __forceinline__ T frcp(T x);
+template <typename T> __device__ __forceinline__ T flog2(T x);
+template <typename T> __device__ __forceinline__ T fexp2(T x);
+template <typename T> __device__ __forceinline__ T fsqrt(T x);
+#if PM_FAST_MATH
+template <> __device__ __forceinline__ float frcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <> __device__ __forceinline__ float flog2<float>(float x) { return __builtin_amdgcn_logf(x); }
+template <> __device__ __forceinline__ float fexp2<float>(float x) { return __builtin_amdgcn_exp2f(x); }
+template <> __device__ __forceinline__ float fsqrt<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
+#else
+template <> __device__ __forceinline__ float frcp<float>(float x) { return 1.0f / x; }
+template <> __device__ __forceinline__ float flog2<float>(float x) { return log2f(x); }
+template <> __device__ __forceinline__ float fexp2<float>(float x) { return exp2f(x); }
+template <> __device__ __forceinline__ float fsqrt<float>(float x) { return sqrtf(x); }
+#endif
+template <> __device__ __forceinline__ double frcp<double>(double x) { return 1.0 / x; }
+template <> __device__ __forceinline__ double flog2<double>(double x) { return log2(x); }
+template <> __device__ __forceinline__ double fexp2<double>(double x) { return exp2(x); }
+template <> __device__ __forceinline__ double fsqrt<double>(double x) { return sqrt(x); }
+
+// Global loads and stores; NT = streaming (non-temporal) hint, used for the
+// aligned population accesses of the step (each value is touched once per
+// step, so keeping it in L2/MALL only evicts useful lines).
+template <typename T, bool NT>
+__device__ __forceinline__ T ldg(const T* a) {
+  if constexpr (NT) return __builtin_nontemporal_load(a);
+  else return *a;
+}
+template <typename T, bool NT>
+__device__ __forceinline__ void stg(T* a, T v) {
+#ifdef PM_EMULATE_FP32_STORAGE
+  v = (T)(float)v;
+#endif
+  if constexpr (NT) __builtin_nontemporal_store(v, a);
+  else *a = v;
+}
+
+// ---- neighbour addressing for the odd (streaming) step ----
+// Source of the pull of direction Q into node (i, j): node (i, j) - e_Q, or
+// the node itself when that crosses a wall.  Returns whether it is inside.
+template <int Q>
+__device__ __forceinline__ bool nbr(int nx, int ny, int px, int py, int i, int j, int sx, int sy,
+                                    int& idx) {
+  // (sx, sy) = +-e_Q direction sign applied by the caller
+  int si = i + sx * EXv[Q], sj = j + sy * EYv[Q];
+  bool in = true;
+  if (EXv[Q] != 0) {
+    if (px) {
+      si = si < 0 ? si + nx : si;
+      si = si >= nx ? si - nx : si;
+    } else {
+      in = in && (si >= 0) && (si < nx);
+    }
+  }
+  if (EYv[Q] != 0) {
+    if (py) {
+      sj = sj < 0 ? sj + ny : sj;
+      sj = sj >= ny ? sj - ny : sj;
+    } else {
+      in = in && (sj >= 0) && (sj < ny);
+    }
+  }
+  idx = sj * nx + si;
+  return in;
+}
+
+template <typename T, int Q>
+__device__ __forceinline__ T pull_f(const KParams<T>& p, int i, int j, int k) {
+  int s;
+  const bool in = nbr<Q>(p.nx, p.ny, p.px, p.py, i, j, -1, -1, s);
+  const T* a = in ? (p.f + OPP[Q] * p.P + s) : (p.f + Q * p.P + k);
+  return ldg<T, EXv[Q] == 0>(a);
+}
+
+template <typename T, int Q>
+__device__ __forceinline__ void push_f(const KParams<T>& p, int i, int j, int k, T v) {
+  int d;
+  const bool in = nbr<Q>(p.nx, p.ny, p.px, p.py, i, j, 1, 1, d);
+  T* a = in ? (p.f + Q * p.P + d) : (p.f + OPP[Q] * p.P + k);
+  stg<T, EXv[Q] == 0>(a, v);
+}
+
+// Thermal pull: across x = 0 the incoming dg_1 is -dg*_3 + hotc (anti-bounce-
+// back, hot wall), across x = nx the incoming dg_3 is -dg*_1 + coldc (cold
+// wall), across y = 0, ny plain bounce-back (adiabatic).
+template <typename T, int Q>
+__device__ __forceinline__ T pull_g(const KParams<T>& p, int i, int j, int k) {
+  int s;
+  const bool in = nbr<Q>(p.nx, p.ny, p.px, p.py, i, j, -1, -1, s);
+  const T* a = in ? (p.g + OPP[Q] * p.P + s) : (p.g + Q * p.P + k);
+  T v = ldg<T, EXv[Q] == 0>(a);
+  if (EXv[Q] == 1) v = in ? v : p.hotc - v;
+  if (EXv[Q] == -1) v = in ? v : p.coldc - v;
+  return v;
+}
+
+template <typename T, int Q>
+__device__ __forceinline__ void push_g(const KParams<T>& p, int i, int j, int k, T v) {
+  int d;
+  const bool in = nbr<Q>(p.nx, p.ny, p.px, p.py, i, j, 1, 1, d);
+  T* a = in ? (p.g + Q * p.P + d) : (p.g + OPP[Q] * p.P + k);
+  T w = v;
+  if (EXv[Q] == -1) w = in ? v : p.hotc - v;  // leaves through x = 0
+  if (EXv[Q] == 1) w = in ? v : p.coldc - v;  // leaves through x = nx
+  stg<T, EXv[Q] == 0>(a, w);
+}
+
+// Interior fast path of the odd step: every neighbour is inside the grid, so
+// the source / destination of direction Q is node k -/+ (e_Qx + e_Qy nx),
+// addressed as a uniform plane base plus a 32-bit offset.
+template <typename T, int Q>
+__device__ __forceinline__ T pull_f_in(const KParams<T>& p, int k) {
+  const T* plane = p.f + OPP[Q] * p.P;
+  return ldg<T, EXv[Q] == 0>(plane + (unsigned)(k - EXv[Q] - EYv[Q] * p.nx));
+}
+template <typename T, int Q>
+__device__ __forceinline__ void push_f_in(const KParams<T>& p, int k, T v) {
+  T* plane = p.f + Q * p.P;
+  stg<T, EXv[Q] == 0>(plane + (unsigned)(k + EXv[Q] + EYv[Q] * p.nx), v);
+}
+template <typename T, int Q>
+__device__ __forceinline__ T pull_g_in(const KParams<T>& p, int k) {
+  const T* plane = p.g + OPP[Q] * p.P;
+  return ldg<T, EXv[Q] == 0>(plane + (unsigned)(k - EXv[Q] - EYv[Q] * p.nx));
+}
+template <typename T, int Q>
+__device__ __forceinline__ void push_g_in(const KParams<T>& p, int k, T v) {
+  T* plane = p.g + Q * p.P;
+  stg<T, EXv[Q] == 0>(plane + (unsigned)(k + EXv[Q] + EYv[Q] * p.nx), v);
+}
+
+template <typename T>
+__device__ __forceinline__ void load_interior_odd(const KParams<T>& p, int k, T df[9], T dg[5]) {
+  df[0] = ldg<T, true>(p.f + (unsigned)k);
+  df[1] = pull_f_in<T, 1>(p, k);
+  df[2] = pull_f_in<T, 2>(p, k);
+  df[3] = pull_f_in<T, 3>(p, k);
+  df[4] = pull_f_in<T, 4>(p, k);
+  df[5] = pull_f_in<T, 5>(p, k);
+  df[6] = pull_f_in<T, 6>(p, k);
+  df[7] = pull_f_in<T, 7>(p, k);
+  df[8] = pull_f_in<T, 8>(p, k);
+  dg[0] = ldg<T, true>(p.g + (unsigned)k);
+  dg[1] = pull_g_in<T, 1>(p, k);
+  dg[2] = pull_g_in<T, 2>(p, k);
+  dg[3] = pull_g_in<T, 3>(p, k);
+  dg[4] = pull_g_in<T, 4>(p, k);
+}
+
+template <typename T>
+__device__ __forceinline__ void store_interior_odd(const KParams<T>& p, int k, const T df[9],
+                                                   const T dg[5]) {
+  stg<T, true>(p.f + (unsigned)k, df[0]);
+  push_f_in<T, 1>(p, k, df[1]);
+  push_f_in<T, 2>(p, k, df[2]);
+  push_f_in<T, 3>(p, k, df[3]);
+  push_f_in<T, 4>(p, k, df[4]);
+  push_f_in<T, 5>(p, k, df[5]);
+  push_f_in<T, 6>(p, k, df[6]);
+  push_f_in<T, 7>(p, k, df[7]);
+  push_f_in<T, 8>(p, k, df[8]);
+  stg<T, true>(p.g + (unsigned)k, dg[0]);
+  push_g_in<T, 1>(p, k, dg[1]);
+  push_g_in<T, 2>(p, k, dg[2]);
+  push_g_in<T, 3>(p, k, dg[3]);
+  push_g_in<T, 4>(p, k, dg[4]);
+}
+
+// Pre-collision populations of node (i, j) for a state of the given parity.
+template <typename T, bool ODD>
+__device__ __forceinline__ void load_node(const KParams<T>& p, int i, int j, T df[9], T dg[5]) {
+  const int k = j * p.nx + i;
+  if (!ODD) {
+#pragma unroll
+    for (int q = 0; q < 9; ++q) df[q] = ldg<T, true>(p.f + q * p.P + k);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) dg[q] = ldg<T, true>(p.g + q * p.P + k);
+  } else {
+    df[0] = ldg<T, true>(p.f + k);
+    df[1] = pull_f<T, 1>(p, i, j, k);
+    df[2] = pull_f<T, 2>(p, i, j, k);
+    df[3] = pull_f<T, 3>(p, i, j, k);
+    df[4] = pull_f<T, 4>(p, i, j, k);
+    df[5] = pull_f<T, 5>(p, i, j, k);
+    df[6] = pull_f<T, 6>(p, i, j, k);
+    df[7] = pull_f<T, 7>(p, i, j, k);
+    df[8] = pull_f<T, 8>(p, i, j, k);
+    dg[0] = ldg<T, true>(p.g + k);
+    dg[1] = pull_g<T, 1>(p, i, j, k);
+    dg[2] = pull_g<T, 2>(p, i, j, k);
+    dg[3] = pull_g<T, 3>(p, i, j, k);
+    dg[4] = pull_g<T, 4>(p, i, j, k);
+  }
+}
+
+template <typename T, bool ODD>
+__device__ __forceinline__ void load_g(const KParams<T>& p, int i, int j, T dg[5]) {
+  const int k = j * p.nx + i;
+  if (!ODD) {
+#pragma unroll
+    for (int q = 0; q < 5; ++q) dg[q] = p.g[q * p.P + k];
+  } else {
+    dg[0] = p.g[k];
+    dg[1] = pull_g<T, 1>(p, i, j, k);
+    dg[2] = pull_g<T, 2>(p, i, j, k);
+    dg[3] = pull_g<T, 3>(p, i, j, k);
+    dg[4] = pull_g<T, 4>(p, i, j, k);
+  }
+}
+
+template <typename T, bool ODD>
+__device__ __forceinline__ void store_node(const KParams<T>& p, int i, int j, const T df[9],
+                                           const T dg[5]) {
+  const int k = j * p.nx + i;
+  if (!ODD) {
+#pragma unroll
+    for (int q = 0; q < 9; ++q) stg<T, true>(p.f + OPP[q] * p.P + k, df[q]);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) stg<T, true>(p.g + OPP[q] * p.P + k, dg[q]);
+  } else {
+    stg<T, true>(p.f + k, df[0]);
+    push_f<T, 1>(p, i, j, k, df[1]);
+    push_f<T, 2>(p, i, j, k, df[2]);
+    push_f<T, 3>(p, i, j, k, df[3]);
+    push_f<T, 4>(p, i, j, k, df[4]);
+    push_f<T, 5>(p, i, j, k, df[5]);
+    push_f<T, 6>(p, i, j, k, df[6]);
+    push_f<T, 7>(p, i, j, k, df[7]);
+    push_f<T, 8>(p, i, j, k, df[8]);
+    stg<T, true>(p.g + k, dg[0]);
+    push_g<T, 1>(p, i, j, k, dg[1]);
+    push_g<T, 2>(p, i, j, k, dg[2]);
+    push_g<T, 3>(p, i, j, k, dg[3]);
+    push_g<T, 4>(p, i, j, k, dg[4]);
+  }
+}
+
+// ---- local viscosity, Eq. (21) with Eqs. (15), (22), (23) ----
+// |gamma|^2 = A + B s^2 with s = 1/(3 nu + 1/2); nu is the unique fixed point
+// of nu = clamp(nu0 (gamma_scale |gamma|)^(n-1), nu_min, nu_max).  With
+// y = log2(nu),
+//   G(y) = y - log2 nu0 - (n-1) (log2 gamma_scale + log2(A + B s^2)/2)
+// is strictly increasing (slope between min(n,1) and max(n,1)), and the
+// clamped fixed point is the unclamped root clamped to [y_lo, y_hi].
+// Start: the root for A << B s^2 and 3 nu >> 1/2, where G is linear in y:
+//   n y0 = log2 nu0 + (n-1) (log2 gamma_scale + log2(B)/2 - log2 3).
+// Then Newton steps, each clamped to [y_lo, y_hi] (iterates that leave the
+// range stay on the bound the root lies beyond).  All lanes of a wave step
+// together until every lane has converged.
+template <typename T>
+__device__ __forceinline__ T solve_nu(const KParams<T>& p, T A, T B) {
+  const T half = T(0.5);
+  const T hn = half * p.nm1;
+  T y = (p.lc0 + p.nm1 * (half * flog2<T>(B) - T(1.584962500721156181453738943947816508))) * p.inv_n;
+  y = fmin(fmax(y, p.y_lo), p.y_hi);  // log2(B = 0) = -inf: lands on a bound
+  for (int it = 0; it < p.max_it; ++it) {
+    const T nu = fexp2<T>(y);
+    const T s = frcp<T>(T(3) * nu + half);
+    const T s2 = s * s;
+    const T g2 = A + B * s2;
+    const T G = (y - p.lc0) - hn * flog2<T>(g2);
+    const T dG = T(1) + T(3) * p.nm1 * B * s2 * s * nu * frcp<T>(g2);
+    T yn = y - G * frcp<T>(dG);
+    // no shear at all (g2 = 0): G = -inf (n < 1) or +inf (n > 1)
+    if (!(g2 > T(0))) yn = G < T(0) ? p.y_hi : p.y_lo;
+    yn = fmin(fmax(yn, p.y_lo), p.y_hi);
+    const bool done = fabs(yn - y) <= p.tol;
+    y = yn;
+    if (__all(done)) break;
+  }
+  return fexp2<T>(y);
+}
+
+template <typename T>
+struct Macro {
+  T rho, ux, uy, T_abs, nu;
+};
+
+// Steps 2-6 of the update for one node (shifted populations in registers):
+// moments, buoyancy, provisional velocity, viscosity, porous velocity.
+template <typename T, bool POW, bool LOGDA>
+__device__ __forceinline__ void node_macros(const KParams<T>& p, int k, const T df[9],
+                                            const T dg[5], T& drho, T& rho, T& jx, T& jy,
+                                            T& dT, T& Gx, T& Gy, T& nu, T& ux, T& uy, T& invK,
+                                            T& invsK, T& m1, T& m7, T& m8) {
+  drho = (df[0] + ((df[1] + df[2]) + (df[3] + df[4]))) + ((df[5] + df[6]) + (df[7] + df[8]));
+  rho = T(1) + drho;
+  jx = ((df[1] - df[3]) + (df[5] - df[6])) - (df[7] - df[8]);
+  jy = ((df[2] - df[4]) + (df[5] + df[6])) - (df[7] + df[8]);
+  dT = dg[0] + ((dg[1] + dg[2]) + (dg[3] + dg[4]));
+  // Step 3: G = (gx, gy + g beta (T - T_m)), T - T_m = dT - (T_m - T_ref)
+  Gx = p.gx;
+  Gy = p.gy + p.gbeta * (dT - p.dTm);
+  // Step 4: provisional velocity v = j/rho + eps G / 2
+  const T irho = frcp<T>(rho);
+  const T vx = jx * irho + T(0.5) * p.eps * Gx;
+  const T vy = jy * irho + T(0.5) * p.eps * Gy;
+  // moments e, pxx, pxy of the shifted populations (rest moments removed)
+  const T s14 = (df[1] + df[2]) + (df[3] + df[4]);
+  const T s58 = (df[5] + df[6]) + (df[7] + df[8]);
+  m1 = (T(-4) * df[0] - s14) + T(2) * s58;
+  m7 = (df[1] - df[2]) + (df[3] - df[4]);
+  m8 = (df[5] - df[6]) + (df[7] - df[8]);
+  // Step 5: viscosity
+  if (POW) {
+    const T vxx = vx * vx, vyy = vy * vy;
+    const T en = (m1 + T(2) * drho) - T(3) * rho * (vxx + vyy) * p.inv_eps;
+    const T pn = m7 - rho * (vxx - vyy) * p.inv_eps;
+    const T qn = m8 - rho * vx * vy * p.inv_eps;
+    const T irho2 = irho * irho;
+    const T A = T(0.25) * p.s_e * p.s_e * en * en * irho2;
+    const T B = T(2.25) * (pn * pn + T(4) * qn * qn) * irho2;
+    nu = solve_nu<T>(p, A, B);
+  } else {
+    nu = p.nu_newt;
+  }
+  // Step 6: porous velocity u = v / (c0 + sqrt(c0^2 + c1 |v|))
+  if (LOGDA) {
+    // K = 10^logDa N^2
+    invK = fexp2<T>(T(-3.321928094887362347870319) * p.logda[k]) * p.inv_Kscale;
+    invsK = fsqrt<T>(invK);
+  } else {
+    invK = p.invK;
+    invsK = p.invsK;
+  }
+  const T c0 = T(0.5) * (T(1) + T(0.5) * p.eps * nu * invK);
+  const T c1 = T(0.5) * p.eps * p.Feps * invsK;
+  const T vm = fsqrt<T>(vx * vx + vy * vy);
+  const T iden = frcp<T>(c0 + fsqrt<T>(c0 * c0 + c1 * vm));
+  ux = vx * iden;
+  uy = vy * iden;
+}
+
+// The full local update: Steps 2-9 on shifted populations, in place.
+template <typename T, bool POW, bool LOGDA>
+__device__ __forceinline__ void collide(const KParams<T>& p, int k, T df[9], T dg[5]) {
+  T drho, rho, jx, jy, dT, Gx, Gy, nu, ux, uy, invK, invsK, m1, m7, m8;
+  node_macros<T, POW, LOGDA>(p, k, df, dg, drho, rho, jx, jy, dT, Gx, Gy, nu, ux, uy, invK,
+                             invsK, m1, m7, m8);
+  // Step 7: force per unit mass (Darcy + Forchheimer drag, eps G)
+  const T um = fsqrt<T>(ux * ux + uy * uy);
+  const T drag = p.eps * nu * invK + p.eps * p.Feps * invsK * um;
+  const T Fx = p.eps * Gx - drag * ux;
+  const T Fy = p.eps * Gy - drag * uy;
+  // Step 8: D2Q9 MRT collision in moment space (shifted moments)
+  const T ie = p.inv_eps;
+  const T uu = ux * ux + uy * uy;
+  const T ruu = T(3) * rho * uu * ie;
+  const T uF = ux * Fx + uy * Fy;
+  const T snu = frcp<T>(T(3) * nu + T(0.5));
+  const T m2 = (T(4) * df[0] - T(2) * ((df[1] + df[2]) + (df[3] + df[4]))) +
+               ((df[5] + df[6]) + (df[7] + df[8]));
+  const T m4 = T(-2) * (df[1] - df[3]) + ((df[5] - df[6]) - (df[7] - df[8]));
+  const T m6 = T(-2) * (df[2] - df[4]) + ((df[5] + df[6]) - (df[7] + df[8]));
+  const T rux = rho * ux, ruy = rho * uy;
+  const T Fm1 = T(6) * rho * uF * ie;
+  const T ms1 = m1 - p.s_e * (m1 - (T(-2) * drho + ruu)) + (T(1) - T(0.5) * p.s_e) * Fm1;
+  const T ms2 = m2 - p.s_eps * (m2 - (drho - ruu)) - (T(1) - T(0.5) * p.s_eps) * Fm1;
+  const T ms3 = rux + T(0.5) * rho * Fx;
+  const T ms4 = m4 - p.s_q * (m4 + rux) - (T(1) - T(0.5) * p.s_q) * rho * Fx;
+  const T ms5 = ruy + T(0.5) * rho * Fy;
+  const T ms6 = m6 - p.s_q * (m6 + ruy) - (T(1) - T(0.5) * p.s_q) * rho * Fy;
+  const T hnu = T(1) - T(0.5) * snu;
+  const T ms7 = m7 - snu * (m7 - rho * (ux * ux - uy * uy) * ie) +
+                hnu * T(2) * rho * (ux * Fx - uy * Fy) * ie;
+  const T ms8 = m8 - snu * (m8 - rho * ux * uy * ie) + hnu * rho * (ux * Fy + uy * Fx) * ie;
+  // back to populations: M^-1 = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4)
+  const T a0 = drho * T(1.0 / 9.0);
+  const T a1 = ms1 * T(1.0 / 36.0), a2 = ms2 * T(1.0 / 36.0);
+  const T a3 = ms3 * T(1.0 / 6.0), a4 = ms4 * T(1.0 / 12.0);
+  const T a5 = ms5 * T(1.0 / 6.0), a6 = ms6 * T(1.0 / 12.0);
+  const T a7 = ms7 * T(0.25), a8 = ms8 * T(0.25);
+  const T b14 = (a0 - a1) - T(2) * a2;
+  const T b58 = (a0 + T(2) * a1) + a2;
+  const T x1 = a3 - T(2) * a4, y1 = a5 - T(2) * a6;
+  const T x5 = a3 + a4, y5 = a5 + a6;
+  df[0] = (a0 - T(4) * a1) + T(4) * a2;
+  df[1] = (b14 + x1) + a7;
+  df[2] = (b14 + y1) - a7;
+  df[3] = (b14 - x1) + a7;
+  df[4] = (b14 - y1) - a7;
+  df[5] = (b58 + x5) + (y5 + a8);
+  df[6] = (b58 - x5) + (y5 - a8);
+  df[7] = (b58 - x5) - (y5 - a8);
+  df[8] = (b58 + x5) - (y5 + a8);
+  // Step 9: D2Q5 MRT thermal collision (flux moments relax to u T)
+  const T Tabs = p.T_ref + dT;
+  const T n1 = dg[1] - dg[3], n2 = dg[2] - dg[4];
+  const T n3 = T(-4) * dg[0] + ((dg[1] + dg[2]) + (dg[3] + dg[4]));
+  const T n4 = (dg[1] - dg[2]) + (dg[3] - dg[4]);
+  const T ns1 = n1 - p.s_g * (n1 - ux * Tabs);
+  const T ns2 = n2 - p.s_g * (n2 - uy * Tabs);
+  const T ns3 = n3 - p.sT_e * (n3 + T(2.0 / 3.0) * dT);
+  const T ns4 = n4 - p.sT_nu * n4;
+  const T c0 = dT * T(0.2), c1 = ns1 * T(0.5), c2 = ns2 * T(0.5);
+  const T c3 = ns3 * T(0.05), c4 = ns4 * T(0.25);
+  const T c03 = c0 + c3;
+  dg[0] = c0 - T(4) * c3;
+  dg[1] = (c03 + c1) + c4;
+  dg[2] = (c03 + c2) - c4;
+  dg[3] = (c03 - c1) + c4;
+  dg[4] = (c03 - c2) - c4;
+}
+
+// One row tile [i0, i0 + TILE) of row j: gather from the state p, collide,
+// scatter into the state d (d == p: the in-place AA update; d != p: the same
+// update written to another buffer, which then holds the complete next
+// state because every slot is written exactly once per step).
+template <typename T, bool ODD, bool POW, bool LOGDA>
+__device__ __forceinline__ void step_tile(const KParams<T>& p, const KParams<T>& d, int i0, int j) {
+  const int i = i0 + threadIdx.x;
+  T df[9], dg[5];
+  if (ODD) {
+    // Waves whose 64 nodes all have their 8 neighbours inside the grid take
+    // the branch-free interior path (wave-uniform test).
+    const int w0 = i0 + (__builtin_amdgcn_readfirstlane(threadIdx.x) & ~63);
+    const bool interior = w0 >= 1 && w0 + 63 <= p.nx - 2 && j >= 1 && j <= p.ny - 2;
+    if (interior) {
+      const int k = j * p.nx + i;
+      load_interior_odd<T>(p, k, df, dg);
+      collide<T, POW, LOGDA>(p, k, df, dg);
+      store_interior_odd<T>(d, k, df, dg);
+      return;
+    }
+  }
+  if (i >= p.nx) return;
+  load_node<T, ODD>(p, i, j, df, dg);
+  collide<T, POW, LOGDA>(p, j * p.nx + i, df, dg);
+  store_node<T, ODD>(d, i, j, df, dg);
+}
+
+}  // namespace dev
+}  // namespace pm

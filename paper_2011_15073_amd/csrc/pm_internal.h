@@ -59,6 +59,20 @@ struct SweepStatus {
   double residual;   // last max |dT| over a chunk
 };
 
+// Constants of the adjoint step, in FP64 (the adjoint recomputes the
+// forward node update in FP64 whatever the storage type of the state).
+// Per-workgroup adjoint partials: sums of the ln nu0, n and s_g derivatives,
+// then the largest |lambda| the workgroup wrote.
+constexpr int ADJ_PART = 4;
+
+struct AdjParams {
+  int nx, ny, has_logda, pow;
+  double eps, inv_eps, Feps, invK, invsK, inv_Kscale, gbeta, dTm, gx, gy;
+  double s_e, s_eps, s_q, s_g, sT_e, sT_nu, T_ref;
+  double nu0, log2nu0, y_lo, y_hi, lc0, nm1, inv_n, log2c;
+  double g2_floor;  // (shear-rate floor)^2, lattice units: below it nu is held fixed
+};
+
 struct Launch {
   hipStream_t stream;
   int tiles_x;     // row tiles of TILE nodes
@@ -77,6 +91,9 @@ constexpr int RED_BLOCKS = 1024; // partial-result slots of the residual
 // parity 0: state in natural layout; 1: after an odd number of steps
 template <typename T>
 hipError_t launch_step(const KParams<T>& p, const Launch& L, int parity, bool pow, bool logda);
+template <typename T>
+hipError_t launch_step_oop(const KParams<T>& src, const KParams<T>& dst, const Launch& L, int parity,
+                           bool pow, bool logda);
 template <typename T>
 hipError_t launch_init(const KParams<T>& p, const Launch& L, T dg_init);
 template <typename T>
@@ -103,6 +120,10 @@ template <typename T>
 hipError_t launch_resid_multi(const SweepCase<T>* cases, int ncases, const int2* sched, int* live,
                               int nsched, int parity, double* partial, SweepStatus* st,
                               int64_t chunk, double tol, int64_t max_steps, hipStream_t s);
+template <typename S>
+hipError_t launch_adjoint(const KParams<S>& st, const AdjParams& a, int parity, const double* lam_next,
+                          double* lam, double* g_logda, double* partial, hipStream_t s);
+hipError_t launch_adjoint_seed(int nx, int ny, double seed, double* lam, hipStream_t s);
 hipError_t launch_write_header(void* dst, int64_t steps, uint64_t tag, hipStream_t s);
 hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, hipStream_t s);
 

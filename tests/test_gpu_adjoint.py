@@ -1,0 +1,235 @@
+"""GPU: the hand-written adjoint against autograd of the independent torch
+FP64 re-implementation of the update, and against central finite
+differences of the forward."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2011_15073_amd as P
+from oracle import torch_step as TS
+from paper_2011_15073_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+PHYS = dict(Pr=10.0, eps=0.6)
+
+
+def torch_vjp(nx, ny, n, Ra, f0, g0, ld, lam, pre_steps):
+    nt = torch.tensor(n, dtype=torch.float64, requires_grad=True)
+    Rat = torch.tensor(Ra, dtype=torch.float64, requires_grad=True)
+    Pm = TS.Params(nx, ny, n=nt, Ra=Rat, **PHYS)
+    ldt = torch.tensor(ld, dtype=torch.float64, requires_grad=True)
+    f, g = torch.from_numpy(f0), torch.from_numpy(g0)
+    with torch.no_grad():
+        Pp = TS.Params(nx, ny, n=n, Ra=Ra, **PHYS)
+        for _ in range(pre_steps):
+            f, g = TS.step(Pp, f, g, torch.from_numpy(ld))
+    f = f.clone().requires_grad_(True)
+    g = g.clone().requires_grad_(True)
+    fn, gn = TS.step(Pm, f, g, ldt)
+    L = (torch.from_numpy(lam[:9]) * fn).sum() + (torch.from_numpy(lam[9:]) * gn).sum()
+    L.backward()
+    return f.grad.numpy(), g.grad.numpy(), ldt.grad.numpy(), nt.grad.item(), Rat.grad.item()
+
+
+@pytest.mark.parametrize("n", [0.7, 1.0, 1.4])
+@pytest.mark.parametrize("grid", [(21, 13), (70, 19)])
+@pytest.mark.parametrize("pre_steps", [0, 1])
+def test_adjoint_step_matches_autograd(n, grid, pre_steps):
+    nx, ny = grid
+    Ra = 1e4
+    f0, g0 = inputs.random_state(nx, ny, seed=7, amp=0.03, amp_T=0.2)
+    ld = inputs.logda_field(max(nx, ny), seed=3)[:ny, :nx].copy()
+    lam = np.random.default_rng(11).standard_normal((14, ny, nx))
+    cav = P.Cavity(nx, ny, dtype="fp64", logda=torch.from_numpy(ld), n=n, Ra=Ra, **PHYS)
+    cav.set_populations(torch.from_numpy(f0), torch.from_numpy(g0))
+    cav.step(pre_steps)
+    lam_g, gld, gn, gRa = P.vjp_step(cav, torch.from_numpy(lam))
+    lam_g = lam_g.cpu().numpy()
+    tf, tg, tld, tn, tRa = torch_vjp(nx, ny, n, Ra, f0, g0, ld, lam, pre_steps)
+    ref = np.concatenate([tf, tg])
+    err = np.abs(lam_g - ref).max() / np.abs(ref).max()
+    print(f"n={n} {grid} pre={pre_steps}: lam err {err:.2e}, dn {gn:.6e} vs {tn:.6e}, dRa {gRa:.6e} vs {tRa:.6e}")
+    assert err <= 1e-11
+    assert np.abs(gld.cpu().numpy() - tld).max() <= 1e-10 * np.abs(tld).max()
+    assert gn == pytest.approx(tn, rel=1e-9, abs=1e-12 * abs(tn) + 1e-14)
+    assert gRa == pytest.approx(tRa, rel=1e-9, abs=1e-14)
+
+
+def nu_after(N, T, ld, n, Ra, dtype="fp64"):
+    c = P.Cavity(N, dtype=dtype, logda=torch.as_tensor(ld), n=n, Ra=Ra, **PHYS)
+    c.step(T)
+    return c.nu()
+
+
+def test_adjoint_trajectory_matches_autograd():
+    """Full trajectory (checkpointed, replayed segments) vs autograd through
+    the torch re-implementation: 12 x 12 cavity, 40 steps."""
+    N, T, n, Ra = 12, 40, 0.7, 1e4
+    ld = inputs.logda_field(N, seed=5)
+    cav = P.Cavity(N, dtype="fp64", logda=torch.from_numpy(ld), n=n, Ra=Ra, **PHYS)
+    adj = P.Adjoint(cav, T, 7)
+    J = adj.forward()
+    gld, gn, gRa = adj.backward()
+    nt = torch.tensor(n, dtype=torch.float64, requires_grad=True)
+    Rat = torch.tensor(Ra, dtype=torch.float64, requires_grad=True)
+    ldt = torch.tensor(ld, requires_grad=True)
+    Pm = TS.Params(N, N, n=nt, Ra=Rat, **PHYS)
+    f, g = TS.rest_state(Pm)
+    for _ in range(T):
+        f, g = TS.step(Pm, f, g, ldt)
+    Jt = TS.nu_bar(Pm, g)
+    Jt.backward()
+    assert J == pytest.approx(Jt.item(), rel=1e-12)
+    assert np.abs(gld.cpu().numpy() - ldt.grad.numpy()).max() <= 1e-9 * np.abs(ldt.grad.numpy()).max()
+    assert gn == pytest.approx(nt.grad.item(), rel=1e-8)
+    assert gRa == pytest.approx(Rat.grad.item(), rel=1e-8)
+
+
+def test_adjoint_matches_finite_differences_fp64():
+    N, T, n, Ra = 32, 400, 0.7, 1e4
+    ld = inputs.logda_field(N, seed=9)
+    cav = P.Cavity(N, dtype="fp64", logda=torch.from_numpy(ld), n=n, Ra=Ra, **PHYS)
+    adj = P.Adjoint(cav, T)
+    adj.forward()
+    gld, gn, gRa = adj.backward()
+    gld = gld.cpu().numpy()
+    h = 1e-4
+    for cell in inputs.fd_cells(N, seed=2, k=6):
+        j, i = divmod(int(cell), N)
+        lp, lm = ld.copy(), ld.copy()
+        lp[j, i] += h
+        lm[j, i] -= h
+        fd = (nu_after(N, T, lp, n, Ra) - nu_after(N, T, lm, n, Ra)) / (2 * h)
+        assert fd == pytest.approx(gld[j, i], rel=1e-5, abs=1e-6 * np.abs(gld).max())
+    fdn = (nu_after(N, T, ld, n * (1 + 1e-5), Ra) - nu_after(N, T, ld, n * (1 - 1e-5), Ra)) / (2e-5 * n)
+    fdR = (nu_after(N, T, ld, n, Ra * (1 + 1e-5)) - nu_after(N, T, ld, n, Ra * (1 - 1e-5))) / (2e-5 * Ra)
+    assert gn == pytest.approx(fdn, rel=1e-5)
+    assert gRa == pytest.approx(fdR, rel=1e-5)
+
+
+def test_nusselt_autograd_function():
+    N, T = 24, 120
+    ld = torch.from_numpy(inputs.logda_field(N, seed=4)).requires_grad_(True)
+    n = torch.tensor(0.8, dtype=torch.float64, requires_grad=True)
+    Ra = torch.tensor(1e4, dtype=torch.float64, requires_grad=True)
+    J = P.nusselt(ld, n, Ra, T=T, dtype="fp64", **PHYS)
+    (2.0 * J).backward()
+    cav = P.Cavity(N, dtype="fp64", logda=ld.detach(), n=0.8, Ra=1e4, **PHYS)
+    adj = P.Adjoint(cav, T)
+    J2 = adj.forward()
+    gld, gn, gRa = adj.backward(seed=2.0)
+    assert J.item() == J2
+    assert torch.equal(ld.grad, gld.cpu())
+    assert n.grad.item() == gn and Ra.grad.item() == gRa
+
+
+# The 256 x 256 adjoint workload: per-cell log10 Da ~ U[-3, -1] (seed 0),
+# J = Nu_bar after 5000 steps from rest, gradients with respect to 16 seeded
+# cells, n and Ra.
+N4, T4 = 256, 5000
+
+
+def fd_cells_check(kw, dtype, h_cell=1e-2, h_rel=1e-4, tol=1e-3):
+    ld = inputs.logda_field(N4, seed=0)
+    base = dict(PHYS, n=0.7, Ra=1e4)
+    base.update(kw)
+    n, Ra = base.pop("n"), base.pop("Ra")
+
+    def J_of(l_, n_, Ra_):
+        c = P.Cavity(N4, dtype="fp64", logda=torch.as_tensor(l_), n=n_, Ra=Ra_, **base)
+        c.step(T4)
+        return c.nu()
+
+    cav = P.Cavity(N4, dtype=dtype, logda=torch.from_numpy(ld), n=n, Ra=Ra, **base)
+    adj = P.Adjoint(cav, T4)
+    J = adj.forward()
+    gld, gn, gRa = adj.backward()
+    g = gld.cpu().numpy()
+    scale = np.abs(g).max()
+    print(f"{kw} {dtype}: J = {J:.8f}, dJ/dn = {gn:.6e}, dJ/dRa = {gRa:.6e}, max|dJ/dlogDa| = {scale:.3e}",
+          flush=True)
+    for cell in inputs.fd_cells(N4, seed=1, k=16):
+        j, i = divmod(int(cell), N4)
+        lp, lm = ld.copy(), ld.copy()
+        lp[j, i] += h_cell
+        lm[j, i] -= h_cell
+        fd = (J_of(lp, n, Ra) - J_of(lm, n, Ra)) / (2 * h_cell)
+        print(f"  cell ({i},{j}): adjoint {g[j, i]:.6e} fd {fd:.6e}", flush=True)
+        assert abs(fd - g[j, i]) <= tol * max(abs(fd), scale)
+    fdn = (J_of(ld, n * (1 + h_rel), Ra) - J_of(ld, n * (1 - h_rel), Ra)) / (2 * h_rel * n)
+    fdR = (J_of(ld, n, Ra * (1 + h_rel)) - J_of(ld, n, Ra * (1 - h_rel))) / (2 * h_rel * Ra)
+    print(f"  dn: adjoint {gn:.6e} fd {fdn:.6e}; dRa: adjoint {gRa:.6e} fd {fdR:.6e}", flush=True)
+    assert gn == pytest.approx(fdn, rel=tol)
+    assert gRa == pytest.approx(fdR, rel=tol)
+
+
+@pytest.mark.parametrize("kw,dtype", [(dict(n=1.0), "fp32"), (dict(n=1.4), "fp32"),
+                                      (dict(n=0.7, nu_hi=2.0), "fp64")],
+                         ids=["n1.0-fp32", "n1.4-fp32", "n0.7-clamp2-fp64"])
+def test_256_cavity_gradients_match_finite_differences(kw, dtype):
+    """The 256 x 256 / 5000-step adjoint workload where Nu_bar is a smooth
+    function of the parameters: central differences of the FP64 forward
+    (h = 1e-2 in log10 Da, 1e-4 relative in n and Ra) within 1e-3 relative
+    (floor 1e-3 max|g| for near-zero cells).  With the [0.1, 2] clamp the FP32
+    forward state is compared in FP64: its own round-off moves the smallest
+    cell gradients by up to 2e-3 of that floor."""
+    fd_cells_check(kw, dtype)
+
+
+def test_256_cavity_n07_exact_adjoint_reports_amplification():
+    """n = 0.7 with the [0.1, 10] clamp: the linearised update amplifies
+    perturbations in low-shear porous regions (the slope of the power law
+    grows like gamma^(n-2) towards zero shear and feeds the Darcy drag), so
+    the exact discrete adjoint grows without bound; the library reports it."""
+    ld = inputs.logda_field(N4, seed=0)
+    cav = P.Cavity(N4, dtype="fp32", logda=torch.from_numpy(ld), n=0.7, Ra=1e4, **PHYS)
+    adj = P.Adjoint(cav, T4)
+    adj.forward()
+    with pytest.raises(P.PmError, match="amplifies perturbations"):
+        adj.backward()
+
+
+def test_256_cavity_n07_regularised_adjoint_tracks_large_step_differences():
+    """Same workload with the shear floor gamma* = 0.1: the regularised
+    gradient follows central differences taken with steps large enough to
+    rise above Nu_bar's step-to-step sensitivity floor (h = 1e-2): n and Ra
+    within 1e-2, a smooth whole-field direction within 1e-1."""
+    ld = inputs.logda_field(N4, seed=0)
+    cav = P.Cavity(N4, dtype="fp32", logda=torch.from_numpy(ld), n=0.7, Ra=1e4, **PHYS)
+    adj = P.Adjoint(cav, T4, shear_floor=0.1)
+    adj.forward()
+    gld, gn, gRa = adj.backward()
+    g = gld.cpu().numpy()
+    assert np.isfinite(g).all()
+    rng = np.random.default_rng(5)
+    y, x = np.mgrid[0:N4, 0:N4] / N4
+    w = sum(rng.standard_normal() * np.cos(math.pi * a * x) * np.cos(math.pi * b * y)
+            for a in range(3) for b in range(3))
+    h = 1e-2
+    fdw = (nu_after(N4, T4, ld + h * w, 0.7, 1e4) - nu_after(N4, T4, ld - h * w, 0.7, 1e4)) / (2 * h)
+    fdn = (nu_after(N4, T4, ld, 0.7 * (1 + h), 1e4) - nu_after(N4, T4, ld, 0.7 * (1 - h), 1e4)) / (2 * h * 0.7)
+    fdR = (nu_after(N4, T4, ld, 0.7, 1e4 * (1 + h)) - nu_after(N4, T4, ld, 0.7, 1e4 * (1 - h))) / (2 * h * 1e4)
+    gw = float((g * w).sum())
+    print(f"<g,w> {gw:.6e} fd {fdw:.6e}; dn {gn:.6e} fd {fdn:.6e}; dRa {gRa:.6e} fd {fdR:.6e}", flush=True)
+    assert gn == pytest.approx(fdn, rel=1e-2)
+    assert gRa == pytest.approx(fdR, rel=1e-2)
+    assert gw == pytest.approx(fdw, rel=1e-1)
+
+
+def test_shear_floor_below_every_shear_rate_is_exact():
+    N, T = 32, 300
+    ld = inputs.logda_field(N, seed=9)
+    out = []
+    for floor in (0.0, 1e-30):
+        cav = P.Cavity(N, dtype="fp64", logda=torch.from_numpy(ld), n=1.4, Ra=1e4, **PHYS)
+        adj = P.Adjoint(cav, T, shear_floor=floor)
+        adj.forward()
+        out.append(adj.backward())
+    assert torch.equal(out[0][0], out[1][0])
+    assert out[0][1] == out[1][1] and out[0][2] == out[1][2]
+    cav = P.Cavity(N, dtype="fp64", logda=torch.from_numpy(ld), n=1.4, Ra=1e4, **PHYS)
+    with pytest.raises(P.PmError):
+        P.Adjoint(cav, T, shear_floor=-1.0)
