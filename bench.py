@@ -34,7 +34,9 @@ BYTES_PER_NODE = 112  # 14 FP32 populations, each read once and written once
 HBM_PEAK_GBS = 8000.0
 CHECK_EVERY = 1000
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_fp32_4096_traffic.txt")
-KERNEL_SRC = os.path.join(ROOT, "paper_2011_15073_amd", "csrc", "pm_kernels.hip")
+# the step kernel's source: the kernel file and the per-node device code it includes
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2011_15073_amd", "csrc", f)
+               for f in ("pm_kernels.hip", "pm_device.h", "pm_internal.h")]
 
 
 def log(*a):
@@ -42,8 +44,11 @@ def log(*a):
 
 
 def kernel_hash():
-    with open(KERNEL_SRC, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def read_traffic():
