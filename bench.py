@@ -149,6 +149,57 @@ def sweep_main(args):
         "steps_per_case": steps}), flush=True)
 
 
+# The paper's own runs and printed Nusselt numbers: its validation table
+# (clear power-law fluid, Ra = 1e5, Pr = 100) and its parametric table
+# (160 x 160, Pr = 6.2; n, Da and Ra varied in turn).  Read literally: the
+# paper's equations have the Darcy term only, so eps = 1 and no Forchheimer
+# term; the validation runs are a clear fluid (Da = inf).
+PAPER_TABLES = os.path.join(ROOT, "tests", "golden", "paper_nu_tables.json")
+
+
+def paper_cases(N):
+    """(sweep case, label dict, paper Nu) for every row of both tables."""
+    tab = json.load(open(PAPER_TABLES))
+    out = []
+    for r in tab["validation"]:
+        out.append((dict(nx=N, n=r["n"], Ra=r["Ra"], Pr=r["Pr"], eps=1.0, forchheimer=0, dtype="fp64"),
+                    dict(table="validation", n=r["n"], Da=None, Ra=r["Ra"], Pr=r["Pr"]), r["nu"]))
+    for r in tab["parametric"]:
+        out.append((dict(nx=N, n=r["n"], Da=r["Da"], Ra=r["Ra"], Pr=r["Pr"], eps=1.0, forchheimer=0,
+                         dtype="fp64"),
+                    dict(table="parametric", n=r["n"], Da=r["Da"], Ra=r["Ra"], Pr=r["Pr"]), r["nu"]))
+    return out
+
+
+def paper_main(args):
+    """Both of the paper's tables run to steady state as one batched sweep
+    (FP64, max|dT| over 1000 steps < tol); prints our Nu beside the paper's."""
+    import torch
+    import paper_2011_15073_amd as P
+
+    N = args.paper_side
+    rows_in = paper_cases(N)
+    cases = [c for c, _, _ in rows_in]
+    sw = P.Sweep(cases)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    steps, res = sw.run(tol=args.sweep_tol, check_every=1000, max_steps=args.sweep_cap,
+                        progress=lambda nl, st: log(f"paper: {nl} live, max steps {max(st)}"))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    rows = []
+    for i, (_, par, nu_p) in enumerate(rows_in):
+        nu = sw.case(i).nu()
+        rows.append(dict(**par, steps=steps[i], residual=res[i], nu=round(nu, 6),
+                         nu_paper=nu_p, rel_diff=round(nu / nu_p - 1.0, 4)))
+        log(f"paper: {par}: Nu {nu:.6f} (paper {nu_p}), {steps[i]} steps, r {res[i]:.1e}")
+    print(json.dumps({"metric": "paper tables: Nu", "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+                      "config": {"workload": f"the paper's validation and parametric cases, {N}x{N}, "
+                                             "eps=1, Darcy drag only, Ma=0.1", "tol": args.sweep_tol,
+                                 "max_steps": args.sweep_cap},
+                      "wall_s": round(wall, 2), "cases": rows}), flush=True)
+
+
 def adjoint_main(args):
     """Cost of the gradient of Nu_bar on the 256 x 256 cavity (FP32 forward
     state, FP64 adjoint, n = 0.7, Ra = 1e4, per-cell log10 Da ~ U[-3, -1]
@@ -204,6 +255,9 @@ def main():
     ap.add_argument("--sweep-dtype", default="fp64", choices=["fp32", "fp64"])
     ap.add_argument("--sweep-tol", type=float, default=1e-8)
     ap.add_argument("--sweep-cap", type=int, default=3_000_000)
+    ap.add_argument("--paper-tables", action="store_true",
+                    help="run the paper's validation and parametric cases and print Nu beside its values")
+    ap.add_argument("--paper-side", type=int, default=160)
     ap.add_argument("--adjoint", action="store_true",
                     help="time the gradient of Nu (forward with checkpoints vs backward)")
     ap.add_argument("--adjoint-steps", type=int, default=5000)
@@ -218,6 +272,8 @@ def main():
     if args.sweep:
         sweep_main(args)
         return
+    if args.paper_tables:
+        return paper_main(args)
     if args.adjoint:
         adjoint_main(args)
         return

@@ -24,7 +24,7 @@ PM_CLAMP_NU, PM_CLAMP_GAMMA = 0, 1
 EXPORTS = [
     "pm_params_default", "pm_lattice_of", "pm_workspace_bytes", "pm_init", "pm_destroy",
     "pm_set_logda", "pm_step", "pm_steps_done", "pm_nu", "pm_residual", "pm_run_to_steady",
-    "pm_fields", "pm_viscosity", "pm_get_populations", "pm_set_populations",
+    "pm_fields", "pm_stream_function", "pm_viscosity", "pm_get_populations", "pm_set_populations",
     "pm_state_bytes", "pm_save_state", "pm_load_state", "pm_copy_probe",
     "pm_sweep_workspace_bytes", "pm_sweep_create", "pm_sweep_set_order", "pm_sweep_run",
     "pm_sweep_advance", "pm_sweep_status",
@@ -88,6 +88,7 @@ def _load():
         "pm_run_to_steady": ([vp, dbl, i64, i64, P(i64), P(dbl)], i32),
         "pm_fields": ([vp, vp, vp, vp, i32], i32),
         "pm_viscosity": ([vp, vp, i32], i32),
+        "pm_stream_function": ([vp, vp, i32], i32),
         "pm_get_populations": ([vp, vp, vp, i32], i32),
         "pm_set_populations": ([vp, vp, vp, i32], i32),
         "pm_state_bytes": ([vp, P(sz)], i32),

@@ -109,6 +109,14 @@ class Cavity:
         self._check(lib.pm_fields(self._h, *(C.c_void_p(t.data_ptr()) for t in out), code))
         return tuple(out)
 
+    def stream_function(self, dtype=torch.float64):
+        """Nondimensional stream function psi [ny, nx] (psi = 0 on the bottom
+        wall; U = d psi / dY, V = -d psi / dX)."""
+        code = _dt_code(dtype)
+        out = torch.empty((self.ny, self.nx), dtype=_TORCH_DT[code], device=self.device)
+        self._check(lib.pm_stream_function(self._h, C.c_void_p(out.data_ptr()), code))
+        return out
+
     def viscosity(self, dtype=torch.float64):
         code = _dt_code(dtype)
         out = torch.empty((self.ny, self.nx), dtype=_TORCH_DT[code], device=self.device)

@@ -467,6 +467,19 @@ int pm_fields(pm_ctx* c, void* U, void* V, void* theta, int dtype) {
   return check_hip(c, e, "pm_fields");
 }
 
+int pm_stream_function(pm_ctx* c, void* psi, int dtype) {
+  if (!c || !psi) return PM_EINVAL;
+  if (!dtype_ok(dtype)) return ctx_fail(c, PM_EINVAL, "pm_stream_function: bad dtype");
+  const int parity = (int)(c->steps & 1);
+  hipError_t e = dispatch(c, [&](auto& kp) {
+    return pm::launch_fields(kp, c->launch, parity, c->pow, c->p.has_logda != 0, psi, nullptr,
+                             nullptr, nullptr, dtype == PM_FP64);
+  });
+  if (e == hipSuccess)
+    e = pm::launch_stream_y(psi, c->p.nx, c->p.ny, 1.0 / (double)c->p.nx, dtype == PM_FP64, c->stream);
+  return check_hip(c, e, "pm_stream_function");
+}
+
 int pm_viscosity(pm_ctx* c, void* nu, int dtype) {
   if (!c || !nu) return PM_EINVAL;
   if (!dtype_ok(dtype)) return ctx_fail(c, PM_EINVAL, "pm_viscosity: bad dtype");

@@ -125,6 +125,7 @@ hipError_t launch_adjoint(const KParams<S>& st, const AdjParams& a, int parity, 
                           double* lam, double* g_logda, double* partial, hipStream_t s);
 hipError_t launch_adjoint_seed(int nx, int ny, double seed, double* lam, hipStream_t s);
 hipError_t launch_write_header(void* dst, int64_t steps, uint64_t tag, hipStream_t s);
+hipError_t launch_stream_y(void* psi, int nx, int ny, double inv_L, int out_fp64, hipStream_t s);
 hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, hipStream_t s);
 
 }  // namespace pm

@@ -278,6 +278,25 @@ __global__ void k_header(int64_t* dst, int64_t steps, uint64_t tag) {
   }
 }
 
+// Stream function from the U field, in place: on entry psi holds U
+// (nondimensional) at the nodes, on exit psi = (1/L) * integral of U dy from
+// the bottom wall (y = 0, psi = 0) to the node (y = j + 1/2): the cells below
+// the node contribute their full value, the node's own cell half.  One thread
+// per column walks up the rows, so each row access of a wave is contiguous;
+// the running sum is FP64.
+template <typename O>
+__global__ __launch_bounds__(256) void k_stream_y(O* psi, int nx, int ny, double inv_L) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= nx) return;
+  double acc = 0.0;
+  for (int j = 0; j < ny; ++j) {
+    const int64_t k = (int64_t)j * nx + i;
+    const double u = (double)psi[k];
+    psi[k] = (O)((acc + 0.5 * u) * inv_L);
+    acc += u;
+  }
+}
+
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 // One 16-byte vector per thread, streaming (non-temporal) load and store.
@@ -431,6 +450,15 @@ hipError_t launch_set_logda(const KParams<T>& p, const Launch& L, T* dst, const 
 
 hipError_t launch_write_header(void* dst, int64_t steps, uint64_t tag, hipStream_t s) {
   hipLaunchKernelGGL(k_header, dim3(1), dim3(64), 0, s, (int64_t*)dst, steps, tag);
+  return hipGetLastError();
+}
+
+hipError_t launch_stream_y(void* psi, int nx, int ny, double inv_L, int out_fp64, hipStream_t s) {
+  const dim3 grid((unsigned)((nx + 255) / 256));
+  if (out_fp64)
+    hipLaunchKernelGGL((k_stream_y<double>), grid, dim3(256), 0, s, (double*)psi, nx, ny, inv_L);
+  else
+    hipLaunchKernelGGL((k_stream_y<float>), grid, dim3(256), 0, s, (float*)psi, nx, ny, inv_L);
   return hipGetLastError();
 }
 

@@ -35,6 +35,7 @@ class _CaseView:
         self._h = h
         p = sweep.params[i]
         self.nx, self.ny, self.device = p.nx, p.ny, sweep.device
+        self.lattice = _lib.lattice_of(p)
 
     def _c(self, rc):
         return check(rc, self._h)

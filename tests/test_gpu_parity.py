@@ -223,3 +223,30 @@ def test_full_size_4096_fp32_sampled():
     assert max(errs.values()) <= 1e-4 and dnu <= 1e-4
     # far from the walls the fluid is still exactly at rest after 16 steps
     assert np.all(Ug[100:-100, 100:-100] == 0.0) and np.all(Tg[100:-100, 100:-100] == 0.5)
+
+
+def test_stream_function():
+    """psi from the GPU against its definition applied to the oracle's U
+    (midpoint rule up each column, psi = 0 on the bottom wall), FP64; at the
+    steady 64 x 64 Newtonian cavity the top-wall value (each column's net
+    flux) is small, and integrating -V along x from the left wall gives
+    nearly the same psi."""
+    N, steps = 64, 20000
+    cav = gpu_for(N, **CFG0)
+    cav.step(steps)
+    psi = cav.stream_function().cpu().numpy()
+    orc = oracle_for(N, **CFG0).step(steps)
+    U, V, _ = orc.fields()
+    ref = (np.cumsum(U, axis=0) - 0.5 * U) / N
+    scale = np.abs(ref).max()
+    assert np.abs(psi - ref).max() <= 1e-11 * scale
+    top = (np.cumsum(U, axis=0)[-1]) / N
+    psi_x = -(np.cumsum(V, axis=1) - 0.5 * V) / N
+    print(f"max|psi| {scale:.4e}, max|column flux| {np.abs(top).max():.3e}, "
+          f"max|psi_y - psi_x| {np.abs(ref - psi_x).max():.3e}")
+    # both vanish only up to the discretisation error of the nodal velocity
+    # (3e-3 of max|psi| measured at 64 x 64)
+    assert np.abs(top).max() <= 1e-2 * scale
+    assert np.abs(ref - psi_x).max() <= 1e-2 * scale
+    psi32 = cav.stream_function(torch.float32).cpu().numpy()
+    assert np.abs(psi32 - psi).max() <= 1e-6 * scale
