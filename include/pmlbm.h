@@ -36,7 +36,11 @@
  *     enqueues on that stream.  Calls that return host values (pm_nu,
  *     pm_residual, pm_run_to_steady) synchronise that stream.  A context is
  *     not thread-safe.
- *   - Grids are stored as planes [q][ny][nx], x fastest.
+ *   - Every caller-facing array (fields, populations, log10 Da, gradients,
+ *     adjoint states) is a set of planes [q][ny][nx], x fastest.  Inside the
+ *     workspace the populations are row-interleaved (the 14 rows of grid row
+ *     j one after the other); raw states from pm_save_state keep that
+ *     internal layout.
  */
 #ifndef PMLBM_H
 #define PMLBM_H
@@ -168,7 +172,7 @@ int pm_get_populations(pm_ctx* ctx, void* f, void* g, int dtype);
 int pm_set_populations(pm_ctx* ctx, const void* f, const void* g, int dtype);
 
 /* Raw state checkpoint: pm_state_bytes gives the size; save/load copy the
- * population planes plus the step count between the workspace and a caller
+ * population region plus the step count between the workspace and a caller
  * device buffer.  Loading restores the step count.  Async. */
 int pm_state_bytes(const pm_ctx* ctx, size_t* bytes);
 int pm_save_state(pm_ctx* ctx, void* dev_dst, size_t bytes);

@@ -69,14 +69,23 @@ __device__ __forceinline__ void stg(T* a, T v) {
   else *a = v;
 }
 
+// ---- population addressing ----
+// Population q of node (i, j) lives at f[q * qs + j * rs + i] (g likewise);
+// see KParams.  pop_off gives the node part j * rs + i.
+template <typename T>
+__device__ __forceinline__ int64_t pop_off(const KParams<T>& p, int i, int j) {
+  return (int64_t)j * p.rs + i;
+}
+
 // ---- neighbour addressing for the odd (streaming) step ----
 // Source of the pull of direction Q into node (i, j): node (i, j) - e_Q, or
 // the node itself when that crosses a wall.  Returns whether it is inside.
 template <int Q>
 __device__ __forceinline__ bool nbr(int nx, int ny, int px, int py, int i, int j, int sx, int sy,
-                                    int& idx) {
+                                    int& si, int& sj) {
   // (sx, sy) = +-e_Q direction sign applied by the caller
-  int si = i + sx * EXv[Q], sj = j + sy * EYv[Q];
+  si = i + sx * EXv[Q];
+  sj = j + sy * EYv[Q];
   bool in = true;
   if (EXv[Q] != 0) {
     if (px) {
@@ -94,23 +103,23 @@ __device__ __forceinline__ bool nbr(int nx, int ny, int px, int py, int i, int j
       in = in && (sj >= 0) && (sj < ny);
     }
   }
-  idx = sj * nx + si;
   return in;
 }
 
+// o = pop_off(p, i, j) of the node itself.
 template <typename T, int Q>
-__device__ __forceinline__ T pull_f(const KParams<T>& p, int i, int j, int k) {
-  int s;
-  const bool in = nbr<Q>(p.nx, p.ny, p.px, p.py, i, j, -1, -1, s);
-  const T* a = in ? (p.f + OPP[Q] * p.P + s) : (p.f + Q * p.P + k);
+__device__ __forceinline__ T pull_f(const KParams<T>& p, int i, int j, int64_t o) {
+  int si, sj;
+  const bool in = nbr<Q>(p.nx, p.ny, p.px, p.py, i, j, -1, -1, si, sj);
+  const T* a = in ? (p.f + OPP[Q] * p.qs + pop_off(p, si, sj)) : (p.f + Q * p.qs + o);
   return ldg<T, EXv[Q] == 0>(a);
 }
 
 template <typename T, int Q>
-__device__ __forceinline__ void push_f(const KParams<T>& p, int i, int j, int k, T v) {
-  int d;
-  const bool in = nbr<Q>(p.nx, p.ny, p.px, p.py, i, j, 1, 1, d);
-  T* a = in ? (p.f + Q * p.P + d) : (p.f + OPP[Q] * p.P + k);
+__device__ __forceinline__ void push_f(const KParams<T>& p, int i, int j, int64_t o, T v) {
+  int di, dj;
+  const bool in = nbr<Q>(p.nx, p.ny, p.px, p.py, i, j, 1, 1, di, dj);
+  T* a = in ? (p.f + Q * p.qs + pop_off(p, di, dj)) : (p.f + OPP[Q] * p.qs + o);
   stg<T, EXv[Q] == 0>(a, v);
 }
 
@@ -118,10 +127,10 @@ __device__ __forceinline__ void push_f(const KParams<T>& p, int i, int j, int k,
 // back, hot wall), across x = nx the incoming dg_3 is -dg*_1 + coldc (cold
 // wall), across y = 0, ny plain bounce-back (adiabatic).
 template <typename T, int Q>
-__device__ __forceinline__ T pull_g(const KParams<T>& p, int i, int j, int k) {
-  int s;
-  const bool in = nbr<Q>(p.nx, p.ny, p.px, p.py, i, j, -1, -1, s);
-  const T* a = in ? (p.g + OPP[Q] * p.P + s) : (p.g + Q * p.P + k);
+__device__ __forceinline__ T pull_g(const KParams<T>& p, int i, int j, int64_t o) {
+  int si, sj;
+  const bool in = nbr<Q>(p.nx, p.ny, p.px, p.py, i, j, -1, -1, si, sj);
+  const T* a = in ? (p.g + OPP[Q] * p.qs + pop_off(p, si, sj)) : (p.g + Q * p.qs + o);
   T v = ldg<T, EXv[Q] == 0>(a);
   if (EXv[Q] == 1) v = in ? v : p.hotc - v;
   if (EXv[Q] == -1) v = in ? v : p.coldc - v;
@@ -129,143 +138,137 @@ __device__ __forceinline__ T pull_g(const KParams<T>& p, int i, int j, int k) {
 }
 
 template <typename T, int Q>
-__device__ __forceinline__ void push_g(const KParams<T>& p, int i, int j, int k, T v) {
-  int d;
-  const bool in = nbr<Q>(p.nx, p.ny, p.px, p.py, i, j, 1, 1, d);
-  T* a = in ? (p.g + Q * p.P + d) : (p.g + OPP[Q] * p.P + k);
+__device__ __forceinline__ void push_g(const KParams<T>& p, int i, int j, int64_t o, T v) {
+  int di, dj;
+  const bool in = nbr<Q>(p.nx, p.ny, p.px, p.py, i, j, 1, 1, di, dj);
+  T* a = in ? (p.g + Q * p.qs + pop_off(p, di, dj)) : (p.g + OPP[Q] * p.qs + o);
   T w = v;
   if (EXv[Q] == -1) w = in ? v : p.hotc - v;  // leaves through x = 0
   if (EXv[Q] == 1) w = in ? v : p.coldc - v;  // leaves through x = nx
   stg<T, EXv[Q] == 0>(a, w);
 }
 
-// Interior fast path of the odd step: every neighbour is inside the grid, so
-// the source / destination of direction Q is node k -/+ (e_Qx + e_Qy nx),
-// addressed as a uniform plane base plus a 32-bit offset.
-template <typename T, int Q>
-__device__ __forceinline__ T pull_f_in(const KParams<T>& p, int k) {
-  const T* plane = p.f + OPP[Q] * p.P;
-  return ldg<T, EXv[Q] == 0>(plane + (unsigned)(k - EXv[Q] - EYv[Q] * p.nx));
+// Interior fast path of the odd step: every neighbour is inside the grid.
+// Rows j - 1, j, j + 1 are addressed from one wave-uniform base (row j - 1)
+// plus a non-negative 32-bit lane offset.
+template <typename T>
+struct RowBase {
+  T* f;  // p.f + (j - 1) rs
+  T* g;
+};
+template <typename T>
+__device__ __forceinline__ RowBase<T> row_base(const KParams<T>& p, int j) {
+  const int64_t o = (int64_t)(j - 1) * p.rs;
+  return RowBase<T>{p.f + o, p.g + o};
 }
-template <typename T, int Q>
-__device__ __forceinline__ void push_f_in(const KParams<T>& p, int k, T v) {
-  T* plane = p.f + Q * p.P;
-  stg<T, EXv[Q] == 0>(plane + (unsigned)(k + EXv[Q] + EYv[Q] * p.nx), v);
-}
-template <typename T, int Q>
-__device__ __forceinline__ T pull_g_in(const KParams<T>& p, int k) {
-  const T* plane = p.g + OPP[Q] * p.P;
-  return ldg<T, EXv[Q] == 0>(plane + (unsigned)(k - EXv[Q] - EYv[Q] * p.nx));
-}
-template <typename T, int Q>
-__device__ __forceinline__ void push_g_in(const KParams<T>& p, int k, T v) {
-  T* plane = p.g + Q * p.P;
-  stg<T, EXv[Q] == 0>(plane + (unsigned)(k + EXv[Q] + EYv[Q] * p.nx), v);
+// offset of population q of node (i + dx, j + dy) from row j - 1
+template <typename T>
+__device__ __forceinline__ unsigned in_off(const KParams<T>& p, int q, int i, int dx, int dy) {
+  return (unsigned)(q * p.qs + (1 + dy) * p.rs + (i + dx));
 }
 
 template <typename T>
-__device__ __forceinline__ void load_interior_odd(const KParams<T>& p, int k, T df[9], T dg[5]) {
-  df[0] = ldg<T, true>(p.f + (unsigned)k);
-  df[1] = pull_f_in<T, 1>(p, k);
-  df[2] = pull_f_in<T, 2>(p, k);
-  df[3] = pull_f_in<T, 3>(p, k);
-  df[4] = pull_f_in<T, 4>(p, k);
-  df[5] = pull_f_in<T, 5>(p, k);
-  df[6] = pull_f_in<T, 6>(p, k);
-  df[7] = pull_f_in<T, 7>(p, k);
-  df[8] = pull_f_in<T, 8>(p, k);
-  dg[0] = ldg<T, true>(p.g + (unsigned)k);
-  dg[1] = pull_g_in<T, 1>(p, k);
-  dg[2] = pull_g_in<T, 2>(p, k);
-  dg[3] = pull_g_in<T, 3>(p, k);
-  dg[4] = pull_g_in<T, 4>(p, k);
+__device__ __forceinline__ void load_interior_odd(const KParams<T>& p, const RowBase<T>& b, int i,
+                                                  T df[9], T dg[5]) {
+  df[0] = ldg<T, true>(b.f + in_off(p, 0, i, 0, 0));
+#pragma unroll
+  for (int q = 1; q < 9; ++q) {
+    const T* a = b.f + in_off(p, OPP[q], i, -EXv[q], -EYv[q]);
+    df[q] = EXv[q] == 0 ? ldg<T, true>(a) : ldg<T, false>(a);
+  }
+  dg[0] = ldg<T, true>(b.g + in_off(p, 0, i, 0, 0));
+#pragma unroll
+  for (int q = 1; q < 5; ++q) {
+    const T* a = b.g + in_off(p, OPP[q], i, -EXv[q], -EYv[q]);
+    dg[q] = EXv[q] == 0 ? ldg<T, true>(a) : ldg<T, false>(a);
+  }
 }
 
 template <typename T>
-__device__ __forceinline__ void store_interior_odd(const KParams<T>& p, int k, const T df[9],
-                                                   const T dg[5]) {
-  stg<T, true>(p.f + (unsigned)k, df[0]);
-  push_f_in<T, 1>(p, k, df[1]);
-  push_f_in<T, 2>(p, k, df[2]);
-  push_f_in<T, 3>(p, k, df[3]);
-  push_f_in<T, 4>(p, k, df[4]);
-  push_f_in<T, 5>(p, k, df[5]);
-  push_f_in<T, 6>(p, k, df[6]);
-  push_f_in<T, 7>(p, k, df[7]);
-  push_f_in<T, 8>(p, k, df[8]);
-  stg<T, true>(p.g + (unsigned)k, dg[0]);
-  push_g_in<T, 1>(p, k, dg[1]);
-  push_g_in<T, 2>(p, k, dg[2]);
-  push_g_in<T, 3>(p, k, dg[3]);
-  push_g_in<T, 4>(p, k, dg[4]);
+__device__ __forceinline__ void store_interior_odd(const KParams<T>& p, const RowBase<T>& b, int i,
+                                                   const T df[9], const T dg[5]) {
+  stg<T, true>(b.f + in_off(p, 0, i, 0, 0), df[0]);
+#pragma unroll
+  for (int q = 1; q < 9; ++q) {
+    T* a = b.f + in_off(p, q, i, EXv[q], EYv[q]);
+    if (EXv[q] == 0) stg<T, true>(a, df[q]);
+    else stg<T, false>(a, df[q]);
+  }
+  stg<T, true>(b.g + in_off(p, 0, i, 0, 0), dg[0]);
+#pragma unroll
+  for (int q = 1; q < 5; ++q) {
+    T* a = b.g + in_off(p, q, i, EXv[q], EYv[q]);
+    if (EXv[q] == 0) stg<T, true>(a, dg[q]);
+    else stg<T, false>(a, dg[q]);
+  }
 }
 
 // Pre-collision populations of node (i, j) for a state of the given parity.
 template <typename T, bool ODD>
 __device__ __forceinline__ void load_node(const KParams<T>& p, int i, int j, T df[9], T dg[5]) {
-  const int k = j * p.nx + i;
+  const int64_t o = pop_off(p, i, j);
   if (!ODD) {
 #pragma unroll
-    for (int q = 0; q < 9; ++q) df[q] = ldg<T, true>(p.f + q * p.P + k);
+    for (int q = 0; q < 9; ++q) df[q] = ldg<T, true>(p.f + q * p.qs + o);
 #pragma unroll
-    for (int q = 0; q < 5; ++q) dg[q] = ldg<T, true>(p.g + q * p.P + k);
+    for (int q = 0; q < 5; ++q) dg[q] = ldg<T, true>(p.g + q * p.qs + o);
   } else {
-    df[0] = ldg<T, true>(p.f + k);
-    df[1] = pull_f<T, 1>(p, i, j, k);
-    df[2] = pull_f<T, 2>(p, i, j, k);
-    df[3] = pull_f<T, 3>(p, i, j, k);
-    df[4] = pull_f<T, 4>(p, i, j, k);
-    df[5] = pull_f<T, 5>(p, i, j, k);
-    df[6] = pull_f<T, 6>(p, i, j, k);
-    df[7] = pull_f<T, 7>(p, i, j, k);
-    df[8] = pull_f<T, 8>(p, i, j, k);
-    dg[0] = ldg<T, true>(p.g + k);
-    dg[1] = pull_g<T, 1>(p, i, j, k);
-    dg[2] = pull_g<T, 2>(p, i, j, k);
-    dg[3] = pull_g<T, 3>(p, i, j, k);
-    dg[4] = pull_g<T, 4>(p, i, j, k);
+    df[0] = ldg<T, true>(p.f + o);
+    df[1] = pull_f<T, 1>(p, i, j, o);
+    df[2] = pull_f<T, 2>(p, i, j, o);
+    df[3] = pull_f<T, 3>(p, i, j, o);
+    df[4] = pull_f<T, 4>(p, i, j, o);
+    df[5] = pull_f<T, 5>(p, i, j, o);
+    df[6] = pull_f<T, 6>(p, i, j, o);
+    df[7] = pull_f<T, 7>(p, i, j, o);
+    df[8] = pull_f<T, 8>(p, i, j, o);
+    dg[0] = ldg<T, true>(p.g + o);
+    dg[1] = pull_g<T, 1>(p, i, j, o);
+    dg[2] = pull_g<T, 2>(p, i, j, o);
+    dg[3] = pull_g<T, 3>(p, i, j, o);
+    dg[4] = pull_g<T, 4>(p, i, j, o);
   }
 }
 
 template <typename T, bool ODD>
 __device__ __forceinline__ void load_g(const KParams<T>& p, int i, int j, T dg[5]) {
-  const int k = j * p.nx + i;
+  const int64_t o = pop_off(p, i, j);
   if (!ODD) {
 #pragma unroll
-    for (int q = 0; q < 5; ++q) dg[q] = p.g[q * p.P + k];
+    for (int q = 0; q < 5; ++q) dg[q] = p.g[q * p.qs + o];
   } else {
-    dg[0] = p.g[k];
-    dg[1] = pull_g<T, 1>(p, i, j, k);
-    dg[2] = pull_g<T, 2>(p, i, j, k);
-    dg[3] = pull_g<T, 3>(p, i, j, k);
-    dg[4] = pull_g<T, 4>(p, i, j, k);
+    dg[0] = p.g[o];
+    dg[1] = pull_g<T, 1>(p, i, j, o);
+    dg[2] = pull_g<T, 2>(p, i, j, o);
+    dg[3] = pull_g<T, 3>(p, i, j, o);
+    dg[4] = pull_g<T, 4>(p, i, j, o);
   }
 }
 
 template <typename T, bool ODD>
 __device__ __forceinline__ void store_node(const KParams<T>& p, int i, int j, const T df[9],
                                            const T dg[5]) {
-  const int k = j * p.nx + i;
+  const int64_t o = pop_off(p, i, j);
   if (!ODD) {
 #pragma unroll
-    for (int q = 0; q < 9; ++q) stg<T, true>(p.f + OPP[q] * p.P + k, df[q]);
+    for (int q = 0; q < 9; ++q) stg<T, true>(p.f + OPP[q] * p.qs + o, df[q]);
 #pragma unroll
-    for (int q = 0; q < 5; ++q) stg<T, true>(p.g + OPP[q] * p.P + k, dg[q]);
+    for (int q = 0; q < 5; ++q) stg<T, true>(p.g + OPP[q] * p.qs + o, dg[q]);
   } else {
-    stg<T, true>(p.f + k, df[0]);
-    push_f<T, 1>(p, i, j, k, df[1]);
-    push_f<T, 2>(p, i, j, k, df[2]);
-    push_f<T, 3>(p, i, j, k, df[3]);
-    push_f<T, 4>(p, i, j, k, df[4]);
-    push_f<T, 5>(p, i, j, k, df[5]);
-    push_f<T, 6>(p, i, j, k, df[6]);
-    push_f<T, 7>(p, i, j, k, df[7]);
-    push_f<T, 8>(p, i, j, k, df[8]);
-    stg<T, true>(p.g + k, dg[0]);
-    push_g<T, 1>(p, i, j, k, dg[1]);
-    push_g<T, 2>(p, i, j, k, dg[2]);
-    push_g<T, 3>(p, i, j, k, dg[3]);
-    push_g<T, 4>(p, i, j, k, dg[4]);
+    stg<T, true>(p.f + o, df[0]);
+    push_f<T, 1>(p, i, j, o, df[1]);
+    push_f<T, 2>(p, i, j, o, df[2]);
+    push_f<T, 3>(p, i, j, o, df[3]);
+    push_f<T, 4>(p, i, j, o, df[4]);
+    push_f<T, 5>(p, i, j, o, df[5]);
+    push_f<T, 6>(p, i, j, o, df[6]);
+    push_f<T, 7>(p, i, j, o, df[7]);
+    push_f<T, 8>(p, i, j, o, df[8]);
+    stg<T, true>(p.g + o, dg[0]);
+    push_g<T, 1>(p, i, j, o, dg[1]);
+    push_g<T, 2>(p, i, j, o, dg[2]);
+    push_g<T, 3>(p, i, j, o, dg[3]);
+    push_g<T, 4>(p, i, j, o, dg[4]);
   }
 }
 
@@ -450,10 +453,9 @@ __device__ __forceinline__ void step_tile(const KParams<T>& p, const KParams<T>&
     const int w0 = i0 + (__builtin_amdgcn_readfirstlane(threadIdx.x) & ~63);
     const bool interior = w0 >= 1 && w0 + 63 <= p.nx - 2 && j >= 1 && j <= p.ny - 2;
     if (interior) {
-      const int k = j * p.nx + i;
-      load_interior_odd<T>(p, k, df, dg);
-      collide<T, POW, LOGDA>(p, k, df, dg);
-      store_interior_odd<T>(d, k, df, dg);
+      load_interior_odd<T>(p, row_base(p, j), i, df, dg);
+      collide<T, POW, LOGDA>(p, j * p.nx + i, df, dg);
+      store_interior_odd<T>(d, row_base(d, j), i, df, dg);
       return;
     }
   }

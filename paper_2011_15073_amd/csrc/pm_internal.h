@@ -12,13 +12,18 @@ namespace pm {
 // Everything one node update needs, already converted to the compute type.
 // Populations are stored shifted: df_q = f_q - w_q and dg_q = g_q - w_q T_ref
 // (T_ref = 1/2), which keeps FP32 resolution on the small deviations from the
-// rest state.
+// rest state.  Population q of node (i, j) is f[q * qs + j * rs + i] (g
+// likewise).  The library lays the 14 populations of a row out one after the
+// other (row-interleaved: qs = padded nx, rs = 14 qs, g = f + 9 qs); the
+// per-cell planes (log10 Da, the residual snapshot) and every caller-facing
+// field use the natural index k = j * nx + i.
 template <typename T>
 struct KParams {
-  T* f;            // 9 planes of P elements
-  T* g;            // 5 planes
-  const T* logda;  // per-cell log10(Da) plane or nullptr
-  int64_t P;       // plane pitch in elements
+  T* f;            // 9 populations
+  T* g;            // 5 populations
+  const T* logda;  // per-cell log10(Da) plane [ny][nx] or nullptr
+  int64_t qs;      // population stride in elements
+  int64_t rs;      // row stride in elements
   int nx, ny;
   int px, py;      // periodic axes
   // viscosity (power law, Eq. 21)
@@ -82,9 +87,6 @@ struct Launch {
 #ifndef PM_TILE
 #define PM_TILE 256
 #endif
-#ifndef PM_PITCH_SKEW
-#define PM_PITCH_SKEW 0
-#endif
 constexpr int TILE = PM_TILE;   // nodes per workgroup (one row segment)
 constexpr int RED_BLOCKS = 1024; // partial-result slots of the residual
 
@@ -95,7 +97,7 @@ template <typename T>
 hipError_t launch_step_oop(const KParams<T>& src, const KParams<T>& dst, const Launch& L, int parity,
                            bool pow, bool logda);
 template <typename T>
-hipError_t launch_init(const KParams<T>& p, const Launch& L, T dg_init);
+hipError_t launch_init(const KParams<T>& p, const Launch& L, T dg_init, size_t pop_bytes);
 template <typename T>
 hipError_t launch_nu(const KParams<T>& p, const Launch& L, int parity, double* out);
 template <typename T>

@@ -17,9 +17,11 @@
 // and push.  Every population is read once and written once per step: the
 // algorithmic traffic is 14 * 2 * sizeof(T) bytes per node update.
 //
-// Planes are SoA [q][ny][nx] with x fastest; one workgroup of 256 threads
-// covers a 256-node row segment, so every load and store of a wave is a
-// contiguous 256 B (FP32) run; workgroups run in row-major tile order.  The
+// Each grid row stores its 9 + 5 population rows one after the other (x
+// fastest, rows padded to 64 elements), so a node update touches one
+// contiguous block per grid row; one workgroup of 256 threads covers a
+// 256-node row segment, so every load and store of a wave is a contiguous
+// 256 B (FP32) run; workgroups run in row-major tile order.  The
 // streaming hint is used on every access that is not shifted along x (those
 // lines are touched exactly once per step); the x-shifted accesses of the odd
 // step straddle lines that the neighbouring wave also touches, so they keep
@@ -64,17 +66,20 @@ __global__ __launch_bounds__(TILE) void k_step_multi(const SweepCase<T>* __restr
   else step_tile<T, ODD, false, false>(c.p, c.p, i0, j);
 }
 
-// Rest state: df = 0, dg_q = w_q (T_init - T_ref).
+// Rest state: df = 0, dg_q = w_q (T_init - T_ref).  (The padding of the
+// population region is cleared by the launcher.)
 template <typename T>
 __global__ void k_init(KParams<T> p, T dg_init) {
   const int64_t n = (int64_t)p.nx * p.ny;
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
        k += (int64_t)gridDim.x * blockDim.x) {
+    const int j = (int)(k / p.nx), i = (int)(k - (int64_t)j * p.nx);
+    const int64_t o = pop_off(p, i, j);
 #pragma unroll
-    for (int q = 0; q < 9; ++q) p.f[q * p.P + k] = T(0);
-    p.g[k] = dg_init * T(2);  // w_0 = 1/3 = 2 w_1
+    for (int q = 0; q < 9; ++q) p.f[q * p.qs + o] = T(0);
+    p.g[o] = dg_init * T(2);  // w_0 = 1/3 = 2 w_1
 #pragma unroll
-    for (int q = 1; q < 5; ++q) p.g[q * p.P + k] = dg_init;
+    for (int q = 1; q < 5; ++q) p.g[q * p.qs + o] = dg_init;
   }
 }
 
@@ -256,12 +261,12 @@ __global__ __launch_bounds__(TILE) void k_set_pop(KParams<T> p, const I* f, cons
   const int j = blockIdx.y;
   const int i = blockIdx.x * TILE + threadIdx.x;
   if (i >= p.nx) return;
-  const int64_t k = (int64_t)j * p.nx + i, n = (int64_t)p.nx * p.ny;
+  const int64_t k = (int64_t)j * p.nx + i, n = (int64_t)p.nx * p.ny, o = pop_off(p, i, j);
 #pragma unroll
-  for (int q = 0; q < 9; ++q) p.f[q * p.P + k] = (T)((double)f[q * n + k] - (double)w9<T>(q));
+  for (int q = 0; q < 9; ++q) p.f[q * p.qs + o] = (T)((double)f[q * n + k] - (double)w9<T>(q));
 #pragma unroll
   for (int q = 0; q < 5; ++q)
-    p.g[q * p.P + k] = (T)((double)g[q * n + k] - (double)w5<T>(q) * (double)p.T_ref);
+    p.g[q * p.qs + o] = (T)((double)g[q * n + k] - (double)w5<T>(q) * (double)p.T_ref);
 }
 
 template <typename T, typename I>
@@ -370,7 +375,10 @@ hipError_t launch_resid_multi(const SweepCase<T>* cases, int ncases, const int2*
 }
 
 template <typename T>
-hipError_t launch_init(const KParams<T>& p, const Launch& L, T dg_init) {
+hipError_t launch_init(const KParams<T>& p, const Launch& L, T dg_init, size_t pop_bytes) {
+  // whole population region first (row padding included), then the nodes
+  hipError_t e = hipMemsetAsync(p.f, 0, pop_bytes, L.stream);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_init<T>), dim3(grid_for((int64_t)p.nx * p.ny)), dim3(256), 0, L.stream,
                      p, dg_init);
   return hipGetLastError();
@@ -475,7 +483,7 @@ hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, hipStream
   template hipError_t launch_step<T>(const KParams<T>&, const Launch&, int, bool, bool);        \
   template hipError_t launch_step_oop<T>(const KParams<T>&, const KParams<T>&, const Launch&, int, \
                                          bool, bool);                                           \
-  template hipError_t launch_init<T>(const KParams<T>&, const Launch&, T);                      \
+  template hipError_t launch_init<T>(const KParams<T>&, const Launch&, T, size_t);              \
   template hipError_t launch_nu<T>(const KParams<T>&, const Launch&, int, double*);             \
   template hipError_t launch_residual<T>(const KParams<T>&, const Launch&, int, T*, double*,    \
                                          double*, int);                                         \
