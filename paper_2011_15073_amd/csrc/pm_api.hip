@@ -90,6 +90,9 @@ int map_params(const pm_params& p, pm_lattice& L, char* msg, size_t msglen) {
   };
   if (p.nx < 2 || p.ny < 2) return fail("nx and ny must be >= 2");
   if ((double)p.nx * (double)p.ny > 2147483647.0 / 2) return fail("grid too large for 32-bit node indices");
+  // the odd step's interior path addresses three rows of 14 populations with
+  // 32-bit offsets: 42 padded rows must stay below 2^32 elements
+  if (p.nx > 100000000) return fail("nx must be <= 1e8");
   if (p.dtype != PM_FP32 && p.dtype != PM_FP64) return fail("dtype must be PM_FP32 or PM_FP64");
   if (!(p.n > 0.0 && p.n <= 4.0)) return fail("power-law index n must be in (0, 4]");
   if (!(p.Ra > 0.0) || !(p.Pr > 0.0)) return fail("Ra and Pr must be > 0");

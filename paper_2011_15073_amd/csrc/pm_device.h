@@ -19,10 +19,9 @@ constexpr int EYv[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 
 // Workgroup b handles row tile b in row-major order.  Dispatch deals
 // consecutive workgroups round-robin to the 8 XCDs, so at any moment all XCDs
-// stream through one narrow band of each plane; that keeps the HBM accesses
-// of the whole chip within few DRAM pages.  (Giving each XCD its own
-// contiguous band of rows measured 5% slower at 4096^2: eight bands far apart
-// in every plane.)
+// stream through one narrow band of rows, within few DRAM pages.  (Giving
+// each XCD its own contiguous band of rows, or groups of 2-64 consecutive
+// tiles, measured no faster.)
 __device__ __forceinline__ int tile_of_block(int b, int) { return b; }
 
 // Arithmetic helpers.  FP32 uses the hardware approximations directly
