@@ -69,8 +69,7 @@ class PmError(RuntimeError):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(
-            f"{LIB_PATH} is not built; run `python -c \"import __graft_entry__ as g; g.build()\"` "
-            "(or python paper_2011_15073_amd/build.py) first")
+            f"{LIB_PATH} is not built; run `python paper_2011_15073_amd/build.py` first")
     L = C.CDLL(LIB_PATH)
     vp, i32, i64, sz, dbl = C.c_void_p, C.c_int, C.c_int64, C.c_size_t, C.c_double
     P = C.POINTER
@@ -118,7 +117,11 @@ def _load():
         "pm_last_error": ([vp], C.c_char_p),
     }
     for name, (args, res) in sig.items():
-        fn = getattr(L, name)
+        try:
+            fn = getattr(L, name)
+        except AttributeError:
+            raise ImportError(f"{LIB_PATH} does not export {name} (a stale build?); rebuild it with "
+                              "`python paper_2011_15073_amd/build.py`") from None
         fn.argtypes = args
         fn.restype = res
     return L
