@@ -240,11 +240,14 @@ const char* pm_sweep_last_error(const pm_sweep* s);
  * node update recomputed in FP64 (the viscosity of Eq. (21) differentiated
  * through its fixed-point equation, or through the active clamp).  Memory:
  * checkpoints of the state every C steps (C ~ sqrt(T)); each segment is
- * replayed out of place before its adjoint steps run in reverse.  Supported:
- * cavity walls (no periodic axes), PM_CLAMP_NU, no extra body force.  The
- * workspace (caller-owned device memory, 256-byte aligned) holds the
- * checkpoints, the replayed segment, two FP64 adjoint states and per-
- * workgroup partial sums. */
+ * replayed out of place before its adjoint steps run in reverse, the replay
+ * of the next segment overlapping the adjoint steps of the current one on a
+ * second HIP stream that the adjoint creates (with five events; released by
+ * pm_adjoint_destroy).  Supported: cavity walls (no periodic axes),
+ * PM_CLAMP_NU, no extra body force.  The workspace (caller-owned device
+ * memory, 256-byte aligned) holds the ceil(T / C) checkpoints, two buffers
+ * of C + 1 replayed states, two FP64 adjoint states and per-workgroup
+ * partial sums. */
 typedef struct pm_adjoint pm_adjoint;
 
 int pm_adjoint_workspace_bytes(const pm_params* p, int64_t T, int64_t C, size_t* bytes);

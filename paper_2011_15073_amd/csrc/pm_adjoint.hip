@@ -46,8 +46,26 @@ __device__ __forceinline__ NuSol nu_fp64(const AdjParams& a, double A, double B)
     return r;
   }
   const double hn = 0.5 * a.nm1;
-  double y = (a.lc0 + a.nm1 * (0.5 * log2(B) - 1.584962500721156181453738943947816508)) * a.inv_n;
-  y = fmin(fmax(y, a.y_lo), a.y_hi);
+  // Start: the closed-form root for A << B s^2, 3 nu >> 1/2, refined by a few
+  // FP32 Newton steps on the hardware exp2 / log2 / reciprocal (about 1e-6 in
+  // y), so that the FP64 Newton steps below converge in two or three.
+  float yf = (float)((a.lc0 + a.nm1 * (0.5 * log2(B) - 1.584962500721156181453738943947816508)) * a.inv_n);
+  {
+    const float lo = (float)a.y_lo, hi = (float)a.y_hi, lc0 = (float)a.lc0, nm1 = (float)a.nm1;
+    const float Af = (float)A, Bf = (float)B;
+    yf = fminf(fmaxf(yf, lo), hi);
+    for (int it = 0; it < 6; ++it) {
+      const float nu = __builtin_amdgcn_exp2f(yf);
+      const float sf = __builtin_amdgcn_rcpf(3.0f * nu + 0.5f);
+      const float g2 = Af + Bf * sf * sf;
+      if (!(g2 > 0.0f)) break;  // no shear in FP32: leave it to the FP64 steps
+      const float G = (yf - lc0) - 0.5f * nm1 * __builtin_amdgcn_logf(g2);
+      const float dG = 1.0f + 3.0f * nm1 * Bf * sf * sf * sf * nu * __builtin_amdgcn_rcpf(g2);
+      yf = fminf(fmaxf(yf - G * __builtin_amdgcn_rcpf(dG), lo), hi);
+    }
+  }
+  double y = fmin(fmax((double)yf, a.y_lo), a.y_hi);
+  if (!(y == y)) y = a.y_hi;  // NaN start (no shear at all): the FP64 steps decide
   for (int it = 0; it < 60; ++it) {
     const double nu = exp2(y);
     const double s = 1.0 / (3.0 * nu + 0.5);

@@ -991,7 +991,9 @@ struct pm_adjoint {
   int64_t T, C, ncp, s0;
   size_t span;          // bytes of one raw population state (the population region)
   char* cp;             // ncp checkpoints
-  char* seg;            // C + 1 states of the segment being replayed
+  char* seg[2];         // C + 1 states of a replayed segment, double-buffered
+  hipStream_t replay;   // segment replays run here, one segment ahead of the adjoint
+  hipEvent_t ev_start, ev_rep[2], ev_used[2];
   double* lam[2];       // adjoint state, natural layout [14][ny][nx]
   double* partial;      // pm::ADJ_PART doubles per workgroup
   int nblocks;
@@ -1038,7 +1040,7 @@ int adj_layout(const pm_params& p, int64_t T, int64_t C, AdjLayout& A, char* msg
   A.off_cp = o;
   o = align_up(o + A.ncp * align_up(A.span));
   A.off_seg = o;
-  o = align_up(o + (C + 1) * align_up(A.span));
+  o = align_up(o + 2 * (C + 1) * align_up(A.span));
   A.off_lam0 = o;
   o = align_up(o + 14 * nn * sizeof(double));
   A.off_lam1 = o;
@@ -1171,6 +1173,17 @@ int pm_adjoint_create(pm_ctx* c, int64_t T, int64_t C, void* dev_ws, size_t ws_b
   }
   pm_adjoint* a = new (std::nothrow) pm_adjoint();
   if (!a) return PM_EDEVICE;
+  hipError_t e = hipStreamCreateWithFlags(&a->replay, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&a->ev_start, hipEventDisableTiming);
+  for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+    e = hipEventCreateWithFlags(&a->ev_rep[i], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&a->ev_used[i], hipEventDisableTiming);
+  }
+  if (e != hipSuccess) {
+    set_global_err("pm_adjoint_create: %s", hipGetErrorString(e));
+    pm_adjoint_destroy(a);
+    return PM_EDEVICE;
+  }
   a->ctx = c;
   a->T = T;
   a->C = C;
@@ -1178,7 +1191,8 @@ int pm_adjoint_create(pm_ctx* c, int64_t T, int64_t C, void* dev_ws, size_t ws_b
   a->span = A.span;
   char* b = (char*)dev_ws;
   a->cp = b + A.off_cp;
-  a->seg = b + A.off_seg;
+  a->seg[0] = b + A.off_seg;
+  a->seg[1] = a->seg[0] + (C + 1) * align_up(A.span);
   a->lam[0] = (double*)(b + A.off_lam0);
   a->lam[1] = (double*)(b + A.off_lam1);
   a->partial = (double*)(b + A.off_partial);
@@ -1220,31 +1234,57 @@ int pm_adjoint_backward(pm_adjoint* a, double seed, void* grad_logda, double* gr
   if (e != hipSuccess) return adj_fail(a, PM_EDEVICE, "backward setup: %s", hipGetErrorString(e));
   const size_t stride = align_up(a->span);
   const bool logda = c->p.has_logda != 0;
-  int cur = 0;
-  for (int64_t k = a->ncp - 1; k >= 0; --k) {
+  // Replay of segment k: from its checkpoint, out of place, into C + 1 slots
+  // (slot t holds S_{kC + t}), on the replay stream.
+  pm::Launch rl = c->launch;
+  rl.stream = a->replay;
+  auto replay = [&](int64_t k, char* seg) -> hipError_t {
     const int64_t start = k * a->C;
     const int64_t n = std::min(a->C, a->T - start);
-    // replay the segment out of place: slot t holds S_{start + t}
-    e = hipMemcpyAsync(a->seg, a->cp + k * stride, a->span, hipMemcpyDeviceToDevice, c->stream);
-    for (int64_t t = 0; t < n && e == hipSuccess; ++t) {
+    hipError_t r = hipMemcpyAsync(seg, a->cp + k * stride, a->span, hipMemcpyDeviceToDevice, a->replay);
+    for (int64_t t = 0; t < n && r == hipSuccess; ++t) {
       const int parity = (int)((a->s0 + start + t) & 1);
-      char* src = a->seg + t * stride;
-      char* dst = a->seg + (t + 1) * stride;
+      char* src = seg + t * stride;
+      char* dst = seg + (t + 1) * stride;
       if (c->p.dtype == PM_FP64)
-        e = pm::launch_step_oop(slot_params<double>(c, c->k64, src), slot_params<double>(c, c->k64, dst),
-                                c->launch, parity, c->pow, logda);
+        r = pm::launch_step_oop(slot_params<double>(c, c->k64, src), slot_params<double>(c, c->k64, dst), rl,
+                                parity, c->pow, logda);
       else
-        e = pm::launch_step_oop(slot_params<float>(c, c->k32, src), slot_params<float>(c, c->k32, dst),
-                                c->launch, parity, c->pow, logda);
+        r = pm::launch_step_oop(slot_params<float>(c, c->k32, src), slot_params<float>(c, c->k32, dst), rl,
+                                parity, c->pow, logda);
     }
+    return r;
+  };
+  // The replay of segment k - 1 runs while the adjoint steps of segment k
+  // run on the context's stream: buffer b holds segment k, b ^ 1 receives
+  // k - 1 once segment k + 1's adjoint steps have finished reading it.
+  if (e == hipSuccess) e = hipEventRecord(a->ev_start, c->stream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(a->replay, a->ev_start, 0);
+  if (e == hipSuccess) e = replay(a->ncp - 1, a->seg[0]);
+  if (e == hipSuccess) e = hipEventRecord(a->ev_rep[0], a->replay);
+  int cur = 0;
+  for (int64_t k = a->ncp - 1; k >= 0 && e == hipSuccess; --k) {
+    const int b = (int)((a->ncp - 1 - k) & 1);
+    if (k >= 1) {
+      if (k + 1 <= a->ncp - 1) e = hipStreamWaitEvent(a->replay, a->ev_used[b ^ 1], 0);
+      if (e == hipSuccess) e = replay(k - 1, a->seg[b ^ 1]);
+      if (e == hipSuccess) e = hipEventRecord(a->ev_rep[b ^ 1], a->replay);
+    }
+    if (e == hipSuccess) e = hipStreamWaitEvent(c->stream, a->ev_rep[b], 0);
     // adjoint steps in reverse over the segment
+    const int64_t start = k * a->C;
+    const int64_t n = std::min(a->C, a->T - start);
     for (int64_t t = n - 1; t >= 0 && e == hipSuccess; --t) {
       const int parity = (int)((a->s0 + start + t) & 1);
-      e = adj_step(c, a->ap, a->seg + t * stride, parity, a->lam[cur], a->lam[cur ^ 1], (double*)grad_logda,
+      e = adj_step(c, a->ap, a->seg[b] + t * stride, parity, a->lam[cur], a->lam[cur ^ 1], (double*)grad_logda,
                    a->partial);
       cur ^= 1;
     }
-    if (e != hipSuccess) return adj_fail(a, PM_EDEVICE, "backward: %s", hipGetErrorString(e));
+    if (e == hipSuccess) e = hipEventRecord(a->ev_used[b], c->stream);
+  }
+  if (e != hipSuccess) {
+    (void)hipStreamSynchronize(a->replay);
+    return adj_fail(a, PM_EDEVICE, "backward: %s", hipGetErrorString(e));
   }
   std::vector<double> part(pm::ADJ_PART * (size_t)a->nblocks);
   e = hipMemcpyAsync(part.data(), a->partial, part.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream);
@@ -1272,7 +1312,16 @@ int pm_adjoint_set_shear_floor(pm_adjoint* a, double gamma_floor) {
   return PM_OK;
 }
 
-void pm_adjoint_destroy(pm_adjoint* a) { delete a; }
+void pm_adjoint_destroy(pm_adjoint* a) {
+  if (!a) return;
+  if (a->replay) {
+    (void)hipStreamSynchronize(a->replay);
+    (void)hipStreamDestroy(a->replay);
+  }
+  for (hipEvent_t ev : {a->ev_start, a->ev_rep[0], a->ev_rep[1], a->ev_used[0], a->ev_used[1]})
+    if (ev) (void)hipEventDestroy(ev);
+  delete a;
+}
 
 const char* pm_adjoint_last_error(const pm_adjoint* a) { return a ? a->err : g_last_err; }
 
