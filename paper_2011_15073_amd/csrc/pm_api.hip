@@ -42,6 +42,7 @@ struct Layout {
   size_t plane;      // pitch of the per-cell planes (log10 Da, snapshot), elements
   size_t pop_bytes;  // the population region (f and g, padding included)
   size_t off_f, off_g, off_logda, off_snap, off_red, total;
+  size_t off_pair;   // second population region for the two-step kernel (0: none)
 };
 
 // Populations are row-interleaved: row j holds the 9 f rows then the 5 g rows
@@ -54,7 +55,18 @@ struct Layout {
 #define PM_SOA_LAYOUT 0
 #endif
 
-Layout layout_of(const pm_params& p) {
+// Two time steps per pass (pm::launch_step2) for FP32 cavities without a
+// periodic axis: halves the HBM traffic per step at the price of a second
+// population region.  PM_PAIR_STEP=0 builds without it, for comparison.
+#ifndef PM_PAIR_STEP
+#define PM_PAIR_STEP 1
+#endif
+
+bool pair_capable(const pm_params& p) {
+  return PM_PAIR_STEP && p.dtype == PM_FP32 && !p.periodic_x && !p.periodic_y;
+}
+
+Layout layout_of(const pm_params& p, bool pair = false) {
   Layout L{};
   L.elem = p.dtype == PM_FP64 ? 8 : 4;
   const size_t n = (size_t)p.nx * (size_t)p.ny;
@@ -78,6 +90,11 @@ Layout layout_of(const pm_params& p) {
   o = align_up(o + L.plane * L.elem);
   L.off_red = o;
   o = align_up(o + (pm::RED_BLOCKS + 16) * sizeof(double));
+  if (pair) {
+    o = (o + (size_t(1) << 21) - 1) / (size_t(1) << 21) * (size_t(1) << 21);  // 2 MiB, like the base
+    L.off_pair = o;
+    o = align_up(o + L.pop_bytes);
+  }
   L.total = o;
   return L;
 }
@@ -207,6 +224,8 @@ struct pm_ctx {
   int64_t steps;
   pm::KParams<float> k32;
   pm::KParams<double> k64;
+  pm::KParams<float> k32b;  // k32 on the second population region (two-step kernel)
+  bool pair;                // two-step kernel available (FP32 cavity, second region)
   pm::Launch launch;
   bool pow;
   hipGraphExec_t graph[2];  // chunk graphs starting at parity 0 / 1
@@ -235,16 +254,29 @@ hipError_t dispatch(pm_ctx* c, F&& fn) {
   return fn(c->k32);
 }
 
+// k steps from step count start_steps.  With the two-step kernel, whole
+// groups of four steps from an even step count run as two passes (region
+// A -> B -> A, so the state always ends in its own region); the remaining
+// steps use the single-step kernel in place.
 hipError_t enqueue_steps(pm_ctx* c, hipStream_t s, int64_t k, int64_t start_steps) {
   pm::Launch L = c->launch;
   L.stream = s;
   const bool logda = c->p.has_logda != 0;
-  for (int64_t t = 0; t < k; ++t) {
+  auto single = [&](int64_t t) {
     const int parity = (int)((start_steps + t) & 1);
-    hipError_t e = dispatch(c, [&](auto& kp) { return pm::launch_step(kp, L, parity, c->pow, logda); });
-    if (e != hipSuccess) return e;
+    return dispatch(c, [&](auto& kp) { return pm::launch_step(kp, L, parity, c->pow, logda); });
+  };
+  hipError_t e = hipSuccess;
+  int64_t t = 0;
+  if (c->pair) {
+    if ((start_steps & 1) && k > 0) e = single(t++);
+    for (; e == hipSuccess && k - t >= 4; t += 4) {
+      e = pm::launch_step2(c->k32, c->k32b, s, c->pow, logda);
+      if (e == hipSuccess) e = pm::launch_step2(c->k32b, c->k32, s, c->pow, logda);
+    }
   }
-  return hipSuccess;
+  for (; e == hipSuccess && t < k; ++t) e = single(t);
+  return e;
 }
 
 int build_graph(pm_ctx* c, int parity) {
@@ -275,6 +307,8 @@ int sync_read(pm_ctx* c, double* host, const double* dev, int n) {
 }
 
 int dtype_ok(int d) { return d == PM_FP32 || d == PM_FP64; }
+
+int init_ctx(const pm_params* p, void* dev_ws, size_t ws_bytes, void* hip_stream, bool pair, pm_ctx** out);
 
 }  // namespace
 
@@ -315,11 +349,21 @@ int pm_workspace_bytes(const pm_params* p, size_t* bytes) {
   int rc = pm_lattice_of(p, &L);
   if (rc) return rc;
   if (!bytes) return PM_EINVAL;
-  *bytes = layout_of(*p).total;
+  *bytes = layout_of(*p, pair_capable(*p)).total;
   return PM_OK;
 }
 
 int pm_init(const pm_params* p, void* dev_ws, size_t ws_bytes, void* hip_stream, pm_ctx** out) {
+  return p ? init_ctx(p, dev_ws, ws_bytes, hip_stream, pair_capable(*p), out) : PM_EINVAL;
+}
+
+}  // extern "C"
+
+namespace {
+
+// pm_init, with or without the second population region of the two-step
+// kernel (contexts of a sweep go without: the sweep has its own kernels).
+int init_ctx(const pm_params* p, void* dev_ws, size_t ws_bytes, void* hip_stream, bool pair, pm_ctx** out) {
   if (!out) {
     set_global_err("pm_init: null out pointer");
     return PM_EINVAL;
@@ -328,7 +372,7 @@ int pm_init(const pm_params* p, void* dev_ws, size_t ws_bytes, void* hip_stream,
   pm_lattice L;
   int rc = pm_lattice_of(p, &L);
   if (rc) return rc;
-  Layout lay = layout_of(*p);
+  Layout lay = layout_of(*p, pair);
   if (!dev_ws || ws_bytes < lay.total) {
     set_global_err("pm_init: workspace of %zu bytes is smaller than the %zu needed", ws_bytes, lay.total);
     return PM_ESTATE;
@@ -352,6 +396,12 @@ int pm_init(const pm_params* p, void* dev_ws, size_t ws_bytes, void* hip_stream,
   (void)hipGetDevice(&c->device);
   c->k32 = kparams<float>(*p, L, dev_ws, lay);
   c->k64 = kparams<double>(*p, L, dev_ws, lay);
+  c->pair = pair;
+  if (pair) {
+    c->k32b = c->k32;
+    c->k32b.f = (float*)((char*)dev_ws + lay.off_pair + lay.off_f);
+    c->k32b.g = (float*)((char*)dev_ws + lay.off_pair + lay.off_g);
+  }
   c->launch.stream = c->stream;
   c->launch.tiles_x = (p->nx + pm::TILE - 1) / pm::TILE;
   c->launch.ntiles = c->launch.tiles_x * p->ny;
@@ -382,6 +432,10 @@ int pm_init(const pm_params* p, void* dev_ws, size_t ws_bytes, void* hip_stream,
   *out = c;
   return PM_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 void pm_destroy(pm_ctx* c) {
   if (!c) return;
@@ -832,7 +886,7 @@ int pm_sweep_create(const pm_params* cases, int ncases, void* dev_ws, size_t ws_
   s->h_cases.assign(ncases * case_sz, 0);
   int tb = 0;
   for (int i = 0; i < ncases; ++i) {
-    rc = pm_init(&cases[i], base + L.off[i], L.bytes[i], hip_stream, &s->ctx[i]);
+    rc = init_ctx(&cases[i], base + L.off[i], L.bytes[i], hip_stream, false, &s->ctx[i]);
     if (rc) {
       snprintf(s->err, sizeof s->err, "case %d: %s", i, g_last_err);
       set_global_err("%s", s->err);

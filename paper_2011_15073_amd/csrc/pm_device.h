@@ -281,14 +281,15 @@ __device__ __forceinline__ void store_node(const KParams<T>& p, int i, int j, co
 // Start: the root for A << B s^2 and 3 nu >> 1/2, where G is linear in y:
 //   n y0 = log2 nu0 + (n-1) (log2 gamma_scale + log2(B)/2 - log2 3).
 // Then Newton steps, each clamped to [y_lo, y_hi] (iterates that leave the
-// range stay on the bound the root lies beyond).  All lanes of a wave step
-// together until every lane has converged.
+// range stay on the bound the root lies beyond).  The lanes of a wave loop
+// together until every lane has converged; a converged lane stops updating.
 template <typename T>
 __device__ __forceinline__ T solve_nu(const KParams<T>& p, T A, T B) {
   const T half = T(0.5);
   const T hn = half * p.nm1;
   T y = (p.lc0 + p.nm1 * (half * flog2<T>(B) - T(1.584962500721156181453738943947816508))) * p.inv_n;
   y = fmin(fmax(y, p.y_lo), p.y_hi);  // log2(B = 0) = -inf: lands on a bound
+  bool conv = false;
   for (int it = 0; it < p.max_it; ++it) {
     const T nu = fexp2<T>(y);
     const T s = frcp<T>(T(3) * nu + half);
@@ -300,9 +301,13 @@ __device__ __forceinline__ T solve_nu(const KParams<T>& p, T A, T B) {
     // no shear at all (g2 = 0): G = -inf (n < 1) or +inf (n > 1)
     if (!(g2 > T(0))) yn = G < T(0) ? p.y_hi : p.y_lo;
     yn = fmin(fmax(yn, p.y_lo), p.y_hi);
-    const bool done = fabs(yn - y) <= p.tol;
-    y = yn;
-    if (__all(done)) break;
+    // each lane keeps the first iterate whose step is within the tolerance,
+    // so a node's viscosity does not depend on which nodes share its wave
+    if (!conv) {
+      conv = fabs(yn - y) <= p.tol;
+      y = yn;
+    }
+    if (__all(conv)) break;
   }
   return fexp2<T>(y);
 }

@@ -48,6 +48,127 @@ __global__ __launch_bounds__(TILE) void k_step_oop(KParams<T> src, KParams<T> ds
   step_tile<T, ODD, POW, LOGDA>(src, dst, (blockIdx.x - j * tiles_x) * TILE, j);
 }
 
+// ---- two time steps in one pass (FP32, cavity walls) ----
+// Reads the state S_k in its natural layout (k even) from src and writes
+// S_{k+2}, also natural, to dst (another buffer: neighbouring workgroups read
+// the halo of src that this one's outputs cover).  Each workgroup owns a strip
+// of PAIR_W output columns and PAIR_R output rows and marches up its rows:
+//   A. row a: gather S_k, collide (step k) -> post-collision f*;
+//   B. row a - 1: pull f* from rows a - 2 .. a (walls: bounce-back, thermal
+//      anti-bounce-back), collide (step k + 1) -> f**;
+//   C. row a - 2: pull f** from rows a - 3 .. a - 1 -> S_{k+2}, store.
+// Thread t works on column x0 - 2 + t, so step k covers two halo columns on
+// each side and step k + 1 one.  The populations that move along x go
+// through LDS rings of the last three rows; those that do not stay in the
+// thread's registers.  The per-node arithmetic is the single-step kernels'
+// (collide), so two passes of this kernel equal four single steps bit for
+// bit.  (Rings of two rows, with the row below carried in registers, allow
+// five workgroups per CU instead of three but measured 3% slower.)
+#ifndef PM_PAIR_R
+#define PM_PAIR_R 24
+#endif
+constexpr int PAIR_W = TILE - 4;     // output columns per workgroup
+constexpr int PAIR_R = PM_PAIR_R;    // output rows per workgroup
+// populations that move along x, in LDS order: f1 f3 f5 f6 f7 f8 g1 g3
+constexpr int NXS = 8;
+
+struct Still {  // the populations with e_x = 0 of one node: f0 f2 f4 g0 g2 g4
+  float f0, f2, f4, g0, g2, g4;
+};
+
+__device__ __forceinline__ void put_row(float (*ring)[NXS][TILE], int slot, int t, const float df[9],
+                                        const float dg[5], Still& st) {
+  ring[slot][0][t] = df[1];
+  ring[slot][1][t] = df[3];
+  ring[slot][2][t] = df[5];
+  ring[slot][3][t] = df[6];
+  ring[slot][4][t] = df[7];
+  ring[slot][5][t] = df[8];
+  ring[slot][6][t] = dg[1];
+  ring[slot][7][t] = dg[3];
+  st = Still{df[0], df[2], df[4], dg[0], dg[2], dg[4]};
+}
+
+// Pre-collision populations of node (c, b) one step after the post-collision
+// rows held in ring (slots sm, s0, sp = rows b - 1, b, b + 1) and in the
+// registers lo, mid, hi (same rows, this column).
+__device__ __forceinline__ void pull_pair(const KParams<float>& p, float (*ring)[NXS][TILE], int sm, int s0,
+                                          int sp, int t, int c, int b, const Still& lo, const Still& mid,
+                                          const Still& hi, float df[9], float dg[5]) {
+  const bool xl = c - 1 >= 0, xr = c + 1 < p.nx, yb = b - 1 >= 0, yt = b + 1 < p.ny;
+  df[0] = mid.f0;
+  df[1] = xl ? ring[s0][0][t - 1] : ring[s0][1][t];          // from (c-1, b) or own f*3
+  df[2] = yb ? lo.f2 : mid.f4;                                // from (c, b-1) or own f*4
+  df[3] = xr ? ring[s0][1][t + 1] : ring[s0][0][t];          // from (c+1, b) or own f*1
+  df[4] = yt ? hi.f4 : mid.f2;                                // from (c, b+1) or own f*2
+  df[5] = (xl && yb) ? ring[sm][2][t - 1] : ring[s0][4][t];  // from (c-1, b-1) or own f*7
+  df[6] = (xr && yb) ? ring[sm][3][t + 1] : ring[s0][5][t];  // from (c+1, b-1) or own f*8
+  df[7] = (xr && yt) ? ring[sp][4][t + 1] : ring[s0][2][t];  // from (c+1, b+1) or own f*5
+  df[8] = (xl && yt) ? ring[sp][5][t - 1] : ring[s0][3][t];  // from (c-1, b+1) or own f*6
+  dg[0] = mid.g0;
+  dg[1] = xl ? ring[s0][6][t - 1] : p.hotc - ring[s0][7][t];   // hot wall: anti-bounce-back
+  dg[2] = yb ? lo.g2 : mid.g4;
+  dg[3] = xr ? ring[s0][7][t + 1] : p.coldc - ring[s0][6][t];  // cold wall: anti-bounce-back
+  dg[4] = yt ? hi.g4 : mid.g2;
+}
+
+template <bool POW, bool LOGDA>
+__global__ __launch_bounds__(TILE) void k_step2(KParams<float> src, KParams<float> dst) {
+  __shared__ float ring1[3][NXS][TILE];  // f* of rows a - 2 .. a
+  __shared__ float ring2[3][NXS][TILE];  // f** of rows a - 3 .. a - 1
+  const int t = threadIdx.x;
+  const int x0 = blockIdx.x * PAIR_W, y0 = blockIdx.y * PAIR_R;
+  const int c = x0 - 2 + t;
+  const bool col = c >= 0 && c < src.nx;
+  const int y_end = min(y0 + PAIR_R, src.ny);  // output rows [y0, y_end)
+  Still r1m{}, r10{}, r1p{};  // f* of rows a - 2, a - 1, a (this column)
+  Still r2m{}, r20{}, r2p{};  // f** of rows a - 3, a - 2, a - 1
+  int s1 = 0;                 // slot of row a; rows a - 1, a - 2 in s1 - 1, s1 - 2 (mod 3)
+  for (int a = y0 - 2; a <= y_end + 1; ++a, s1 = s1 == 2 ? 0 : s1 + 1) {
+    const int s1m = s1 == 0 ? 2 : s1 - 1, s1mm = s1m == 0 ? 2 : s1m - 1;
+    // A: step k at row a
+    {
+      float df[9], dg[5];
+      Still st{};
+      if (col && a >= 0 && a < src.ny) {
+        load_node<float, false>(src, c, a, df, dg);
+        collide<float, POW, LOGDA>(src, a * src.nx + c, df, dg);
+        put_row(ring1, s1, t, df, dg, st);
+      }
+      r1m = r10;
+      r10 = r1p;
+      r1p = st;
+    }
+    __syncthreads();
+    // B: step k + 1 at row b = a - 1 (ring1 slots s1mm, s1m, s1 = rows b - 1, b, b + 1)
+    const int b = a - 1;
+    {
+      Still st{};
+      if (b >= y0 - 1 && b >= 0 && b < src.ny && col && t >= 1 && t <= TILE - 2) {
+        float df[9], dg[5];
+        pull_pair(src, ring1, s1mm, s1m, s1, t, c, b, r1m, r10, r1p, df, dg);
+        collide<float, POW, LOGDA>(src, b * src.nx + c, df, dg);
+        put_row(ring2, s1m, t, df, dg, st);  // ring2 keeps row r in the slot ring1 gives row r
+      }
+      r2m = r20;
+      r20 = r2p;
+      r2p = st;
+    }
+    __syncthreads();
+    // C: S_{k+2} at row o = a - 2 (rows o - 1, o, o + 1 = a - 3, a - 2, a - 1 in slots s1, s1mm, s1m)
+    const int o = a - 2;
+    if (o >= y0 && o < y_end && t >= 2 && t <= TILE - 3 && c < src.nx) {
+      float df[9], dg[5];
+      pull_pair(src, ring2, s1, s1mm, s1m, t, c, o, r2m, r20, r2p, df, dg);
+      const int64_t off = pop_off(dst, c, o);
+#pragma unroll
+      for (int q = 0; q < 9; ++q) stg<float, true>(dst.f + q * dst.qs + off, df[q]);
+#pragma unroll
+      for (int q = 0; q < 5; ++q) stg<float, true>(dst.g + q * dst.qs + off, dg[q]);
+    }
+  }
+}
+
 // ---- batched parameter sweep: one launch steps every live case ----
 // Workgroup b takes the (case, tile) pair of entry b of the schedule; cases
 // that have met their stopping test are skipped.  Each case runs the same
@@ -333,6 +454,19 @@ hipError_t launch_step(const KParams<T>& p, const Launch& L, int parity, bool po
     else { if (logda) PM_STEP(false, false, true); else PM_STEP(false, false, false); }
   }
 #undef PM_STEP
+  return hipGetLastError();
+}
+
+hipError_t launch_step2(const KParams<float>& src, const KParams<float>& dst, hipStream_t s, bool pow,
+                        bool logda) {
+  const dim3 grid((unsigned)((src.nx + PAIR_W - 1) / PAIR_W), (unsigned)((src.ny + PAIR_R - 1) / PAIR_R));
+  if (pow) {
+    if (logda) hipLaunchKernelGGL((k_step2<true, true>), grid, dim3(TILE), 0, s, src, dst);
+    else hipLaunchKernelGGL((k_step2<true, false>), grid, dim3(TILE), 0, s, src, dst);
+  } else {
+    if (logda) hipLaunchKernelGGL((k_step2<false, true>), grid, dim3(TILE), 0, s, src, dst);
+    else hipLaunchKernelGGL((k_step2<false, false>), grid, dim3(TILE), 0, s, src, dst);
+  }
   return hipGetLastError();
 }
 
