@@ -61,6 +61,10 @@ extern "C" {
 #define PM_FP32 0 /* FP32 storage and arithmetic; FP64 reductions */
 #define PM_FP64 1 /* FP64 storage and arithmetic */
 
+#define PM_STEP_AUTO 0   /* two-step kernel where it pays off (large FP32 cavities) */
+#define PM_STEP_SINGLE 1 /* always one step per pass (in place, AA pattern) */
+#define PM_STEP_PAIR 2   /* two steps per pass wherever allowed (FP32, no periodic axis) */
+
 #define PM_CLAMP_NU 0    /* nu = clamp(nu0 gamma*^(n-1), nu_lo nu0, nu_hi nu0) */
 #define PM_CLAMP_GAMMA 1 /* nu = nu0 clamp(gamma*, nu_lo, nu_hi)^(n-1): the
                             thresholds gamma1, gamma2 of Eq. (21) */
@@ -86,6 +90,11 @@ typedef struct {
   double sT_e, sT_nu;     /* D2Q5 higher-moment rates (default 1.0, 1.0) */
   double gx, gy;          /* extra uniform body force, lattice units (default 0) */
   double T_init;          /* initial uniform theta (default 0.5) */
+  int32_t step_kernel;    /* PM_STEP_AUTO (default), PM_STEP_SINGLE or PM_STEP_PAIR.  Both
+                             kernels give the same populations bit for bit; the two-step
+                             kernel needs a second population region in the workspace
+                             (pm_workspace_bytes accounts for it).  PM_STEP_PAIR with FP64
+                             or a periodic axis is PM_EINVAL. */
 } pm_params;
 
 /* Lattice values derived from pm_params (read-only description). */
@@ -98,7 +107,7 @@ typedef struct {
 
 /* Defaults: nx = ny = 64, n = 1, Da = +inf, Ra = 1e3, Pr = 10, eps = 1,
  * mach = 0.1, nu_lo = 0.1, nu_hi = 10, PM_CLAMP_NU, PM_FP32, forchheimer = 1,
- * has_logda = 0, paper rates, no body force, T_init = 0.5. */
+ * has_logda = 0, paper rates, no body force, T_init = 0.5, PM_STEP_AUTO. */
 int pm_params_default(pm_params* p);
 
 /* Validate p and describe the lattice it maps to.  Host only.  PM_EINVAL if
@@ -193,7 +202,8 @@ int pm_copy_probe(const void* src, void* dst, size_t bytes, void* hip_stream);
  * pm_run_to_steady would stop it, and is then skipped.  The per-node
  * arithmetic is the single-case kernel's, so every case ends bitwise equal to
  * the same case run alone.  All cases must share one dtype; per-cell log-Da
- * planes are not supported.  The workspace (caller-owned device memory,
+ * planes are not supported; every case steps one step per pass (step_kernel
+ * is ignored).  The workspace (caller-owned device memory,
  * 256-byte aligned) holds every case's planes plus the case table,
  * schedule, flags and partial results. */
 typedef struct pm_sweep pm_sweep;

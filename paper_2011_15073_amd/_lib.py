@@ -48,7 +48,8 @@ class PmParams(C.Structure):
                 ("has_logda", C.c_int32),
                 ("s_e", C.c_double), ("s_eps", C.c_double), ("s_q", C.c_double),
                 ("sT_e", C.c_double), ("sT_nu", C.c_double),
-                ("gx", C.c_double), ("gy", C.c_double), ("T_init", C.c_double)]
+                ("gx", C.c_double), ("gy", C.c_double), ("T_init", C.c_double),
+                ("step_kernel", C.c_int32)]
 
 
 class PmLattice(C.Structure):
@@ -140,7 +141,7 @@ def check(rc, ctx=None, errfn=None):
 def make_params(nx, ny=None, *, n=1.0, Da=math.inf, Ra=1e3, Pr=10.0, eps=1.0, mach=0.1,
                 nu_lo=0.1, nu_hi=10.0, clamp_mode=PM_CLAMP_NU, dtype="fp32", forchheimer=1,
                 has_logda=0, s_e=0.0, s_eps=0.0, s_q=0.0, sT_e=0.0, sT_nu=0.0, gx=0.0, gy=0.0,
-                T_init=0.5, periodic_x=0, periodic_y=0) -> PmParams:
+                T_init=0.5, periodic_x=0, periodic_y=0, step_kernel=0) -> PmParams:
     p = PmParams()
     check(lib.pm_params_default(C.byref(p)))
     p.nx, p.ny = int(nx), int(nx if ny is None else ny)
@@ -151,6 +152,7 @@ def make_params(nx, ny=None, *, n=1.0, Da=math.inf, Ra=1e3, Pr=10.0, eps=1.0, ma
     p.forchheimer, p.has_logda = int(forchheimer), int(has_logda)
     p.s_e, p.s_eps, p.s_q, p.sT_e, p.sT_nu = s_e, s_eps, s_q, sT_e, sT_nu
     p.gx, p.gy, p.T_init = gx, gy, T_init
+    p.step_kernel = {"auto": 0, "single": 1, "pair": 2, 0: 0, 1: 1, 2: 2}[step_kernel]
     return p
 
 

@@ -55,15 +55,19 @@ struct Layout {
 #define PM_SOA_LAYOUT 0
 #endif
 
-// Two time steps per pass (pm::launch_step2) for FP32 cavities without a
-// periodic axis: halves the HBM traffic per step at the price of a second
+// Two time steps per pass (pm::launch_step2) for large FP32 cavities without
+// a periodic axis: fewer HBM bytes per step at the price of a second
 // population region.  PM_PAIR_STEP=0 builds without it, for comparison.
 #ifndef PM_PAIR_STEP
 #define PM_PAIR_STEP 1
 #endif
 
 bool pair_capable(const pm_params& p) {
-  return PM_PAIR_STEP && p.dtype == PM_FP32 && !p.periodic_x && !p.periodic_y;
+  if (!PM_PAIR_STEP || p.dtype != PM_FP32 || p.periodic_x || p.periodic_y) return false;
+  if (p.step_kernel == PM_STEP_PAIR) return true;
+  if (p.step_kernel == PM_STEP_SINGLE) return false;
+  const int64_t wg = (int64_t)((p.nx + pm::PAIR_W - 1) / pm::PAIR_W) * ((p.ny + pm::PAIR_R - 1) / pm::PAIR_R);
+  return wg >= pm::PAIR_MIN_WORKGROUPS;
 }
 
 Layout layout_of(const pm_params& p, bool pair = false) {
@@ -123,6 +127,10 @@ int map_params(const pm_params& p, pm_lattice& L, char* msg, size_t msglen) {
     return fail("PM_CLAMP_NU bounds must bracket 1 (nu0 itself)");
   if (!std::isfinite(p.gx) || !std::isfinite(p.gy) || !std::isfinite(p.T_init))
     return fail("gx, gy, T_init must be finite");
+  if (p.step_kernel != PM_STEP_AUTO && p.step_kernel != PM_STEP_SINGLE && p.step_kernel != PM_STEP_PAIR)
+    return fail("step_kernel must be PM_STEP_AUTO, PM_STEP_SINGLE or PM_STEP_PAIR");
+  if (p.step_kernel == PM_STEP_PAIR && (!PM_PAIR_STEP || p.dtype != PM_FP32 || p.periodic_x || p.periodic_y))
+    return fail("PM_STEP_PAIR needs FP32 and cavity walls on both axes");
   const double N = (double)p.nx;
   memset(&L, 0, sizeof L);
   L.U_lb = p.mach / std::sqrt(3.0);

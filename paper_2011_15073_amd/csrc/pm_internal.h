@@ -88,6 +88,20 @@ struct Launch {
 #define PM_TILE 256
 #endif
 constexpr int TILE = PM_TILE;   // nodes per workgroup (one row segment)
+
+// The two-step kernel: a workgroup owns PAIR_W output columns by PAIR_R
+// output rows.  It pays off only with many workgroups: each marches through
+// its rows with two barriers per row, and only three fit a CU (LDS), so the
+// library uses it when the grid gives at least PAIR_MIN_WORKGROUPS of them
+// (three full rounds of 3 workgroups on each of 256 CUs; at 4096^2 it is 20%
+// faster per step than the single-step kernel, at 3072^2 and below equal or
+// slower).
+#ifndef PM_PAIR_R
+#define PM_PAIR_R 24
+#endif
+constexpr int PAIR_W = PM_TILE - 4;
+constexpr int PAIR_R = PM_PAIR_R;
+constexpr int64_t PAIR_MIN_WORKGROUPS = 9 * 256;
 constexpr int RED_BLOCKS = 1024; // partial-result slots of the residual
 
 // parity 0: state in natural layout; 1: after an odd number of steps

@@ -64,11 +64,6 @@ __global__ __launch_bounds__(TILE) void k_step_oop(KParams<T> src, KParams<T> ds
 // (collide), so two passes of this kernel equal four single steps bit for
 // bit.  (Rings of two rows, with the row below carried in registers, allow
 // five workgroups per CU instead of three but measured 3% slower.)
-#ifndef PM_PAIR_R
-#define PM_PAIR_R 24
-#endif
-constexpr int PAIR_W = TILE - 4;     // output columns per workgroup
-constexpr int PAIR_R = PM_PAIR_R;    // output rows per workgroup
 // populations that move along x, in LDS order: f1 f3 f5 f6 f7 f8 g1 g3
 constexpr int NXS = 8;
 

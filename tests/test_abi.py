@@ -93,3 +93,21 @@ def test_workspace_size_covers_planes():
 def test_strerror_codes():
     for code in (0, -1, -2, -3, -4):
         assert _lib.lib.pm_strerror(code)
+
+
+def test_step_kernel_choice():
+    """PM_STEP_PAIR needs FP32 and cavity walls on both axes; the automatic
+    choice takes the two-step kernel (and its second population region) only
+    on grids large enough to fill the GPU."""
+    kw = dict(n=1.0, Da=0.1, Ra=1e3, Pr=10.0, eps=0.6)
+    with pytest.raises(P.PmError):
+        P.workspace_bytes(P.make_params(64, dtype="fp64", step_kernel="pair", **kw))
+    with pytest.raises(P.PmError):
+        P.workspace_bytes(P.make_params(64, dtype="fp32", step_kernel="pair", periodic_x=1, **kw))
+    auto = P.workspace_bytes(P.make_params(256, dtype="fp32", **kw))
+    single = P.workspace_bytes(P.make_params(256, dtype="fp32", step_kernel="single", **kw))
+    pair = P.workspace_bytes(P.make_params(256, dtype="fp32", step_kernel="pair", **kw))
+    assert auto == single < pair
+    big_auto = P.workspace_bytes(P.make_params(4096, dtype="fp32", **kw))
+    big_single = P.workspace_bytes(P.make_params(4096, dtype="fp32", step_kernel="single", **kw))
+    assert big_auto >= big_single + 14 * 4096 * 4096 * 4

@@ -258,17 +258,17 @@ PAIR_SIZES = [(8, 8), (33, 21), (252, 70), (300, 130), (520, 67)]
 @pytest.mark.parametrize("size", PAIR_SIZES)
 @pytest.mark.parametrize("n,logda", [(1.0, False), (0.6, False), (0.8, True)])
 def test_two_step_kernel_equals_single_steps(size, n, logda):
-    """FP32 cavities advance four steps at a time with the two-step kernel
-    (two passes, A -> B -> A); one step at a time uses the single-step kernel
-    in place.  Both must give the same populations bit for bit -- on grids
-    narrower and wider than one 252-column strip, with partial 64-row
-    chunks -- from rest and from a random state, and across a graph-replayed
-    run (k >= 128, starting at an odd step count)."""
+    """The two-step kernel (forced with PM_STEP_PAIR: by default it runs only
+    on grids large enough to fill the GPU) against the single-step kernel:
+    both must give the same populations bit for bit -- on grids narrower and
+    wider than one 252-column strip, with partial 24-row chunks -- from a
+    random state, and across a graph-replayed run (k >= 128, starting at an
+    odd step count)."""
     nx, ny = size
     kw = dict(n=n, Da=1e-2, Ra=1e5, Pr=10.0, eps=0.6)
     ld = inputs.logda_field(max(nx, ny), seed=2)[:ny, :nx].copy() if logda else None
-    a = gpu_for(nx, ny, dtype="fp32", logda=ld, **kw)
-    b = gpu_for(nx, ny, dtype="fp32", logda=ld, **kw)
+    a = gpu_for(nx, ny, dtype="fp32", logda=ld, step_kernel="pair", **kw)
+    b = gpu_for(nx, ny, dtype="fp32", logda=ld, step_kernel="single", **kw)
     f0, g0 = inputs.random_state(nx, ny, seed=21, amp=0.02, amp_T=0.1)
     for c in (a, b):
         c.set_populations(torch.from_numpy(f0).float(), torch.from_numpy(g0).float())
@@ -286,3 +286,4 @@ def test_two_step_kernel_equals_single_steps(size, n, logda):
     assert a.steps == b.steps == 143
     assert torch.equal(fa, fb) and torch.equal(ga, gb)
     assert a.nu() == b.nu()
+
