@@ -174,13 +174,16 @@ __device__ __forceinline__ void vjp_node(const AdjParams& a, const double df[9],
   // Step 8: f* = M^-1 ms
   const double sm58 = (mf[5] + mf[6]) + (mf[7] + mf[8]);
   const double sm14 = (mf[1] + mf[2]) + (mf[3] + mf[4]);
-  const double bm0 = (mf[0] + sm14 + sm58) / 9.0;
-  const double bm1 = (-4.0 * mf[0] - sm14 + 2.0 * sm58) / 36.0;
-  const double bm2 = (4.0 * mf[0] - 2.0 * sm14 + sm58) / 36.0;
-  const double bm3 = ((mf[1] - mf[3]) + (mf[5] - mf[6]) - (mf[7] - mf[8])) / 6.0;
-  const double bm4 = (-2.0 * (mf[1] - mf[3]) + (mf[5] - mf[6]) - (mf[7] - mf[8])) / 12.0;
-  const double bm5 = ((mf[2] - mf[4]) + (mf[5] + mf[6]) - (mf[7] + mf[8])) / 6.0;
-  const double bm6 = (-2.0 * (mf[2] - mf[4]) + (mf[5] + mf[6]) - (mf[7] + mf[8])) / 12.0;
+  // (the row norms 9, 36, 6, 12 of M as multiplications: FP64 division is a
+  // long instruction sequence on this path)
+  constexpr double i9 = 1.0 / 9.0, i36 = 1.0 / 36.0, i6 = 1.0 / 6.0, i12 = 1.0 / 12.0;
+  const double bm0 = (mf[0] + sm14 + sm58) * i9;
+  const double bm1 = (-4.0 * mf[0] - sm14 + 2.0 * sm58) * i36;
+  const double bm2 = (4.0 * mf[0] - 2.0 * sm14 + sm58) * i36;
+  const double bm3 = ((mf[1] - mf[3]) + (mf[5] - mf[6]) - (mf[7] - mf[8])) * i6;
+  const double bm4 = (-2.0 * (mf[1] - mf[3]) + (mf[5] - mf[6]) - (mf[7] - mf[8])) * i12;
+  const double bm5 = ((mf[2] - mf[4]) + (mf[5] + mf[6]) - (mf[7] + mf[8])) * i6;
+  const double bm6 = (-2.0 * (mf[2] - mf[4]) + (mf[5] + mf[6]) - (mf[7] + mf[8])) * i12;
   const double bm7 = ((mf[1] - mf[2]) + (mf[3] - mf[4])) * 0.25;
   const double bm8 = ((mf[5] - mf[6]) + (mf[7] - mf[8])) * 0.25;
   double b_drho = bm0, b_rho = 0.0, b_Fx = 0.0, b_Fy = 0.0, b_snu = 0.0, b_hnu = 0.0;
@@ -269,8 +272,9 @@ __device__ __forceinline__ void vjp_node(const AdjParams& a, const double df[9],
   double b_invsK = eps * a.Feps * um * b_drag;
   const double b_um = eps * a.Feps * invsK * b_drag;
   if (um > 0.0) {
-    b_ux += ux / um * b_um;
-    b_uy += uy / um * b_um;
+    const double ium = 1.0 / um;
+    b_ux += ux * ium * b_um;
+    b_uy += uy * ium * b_um;
   }
 
   // Step 6: u = v / (c0 + sqrt(c0^2 + c1 |v|))
@@ -281,12 +285,14 @@ __device__ __forceinline__ void vjp_node(const AdjParams& a, const double df[9],
   const double b_sq = b_den;
   double b_c1 = 0.0;
   if (sq > 0.0) {
-    b_c0 += c0 / sq * b_sq;
-    b_c1 += 0.5 * vm / sq * b_sq;
-    const double b_vm = 0.5 * c1 / sq * b_sq;
+    const double isq = 1.0 / sq;
+    b_c0 += c0 * isq * b_sq;
+    b_c1 += 0.5 * vm * isq * b_sq;
+    const double b_vm = 0.5 * c1 * isq * b_sq;
     if (vm > 0.0) {
-      b_vx += vx / vm * b_vm;
-      b_vy += vy / vm * b_vm;
+      const double ivm = 1.0 / vm;
+      b_vx += vx * ivm * b_vm;
+      b_vy += vy * ivm * b_vm;
     }
   }
   b_nu += 0.25 * eps * invK * b_c0;
@@ -305,15 +311,17 @@ __device__ __forceinline__ void vjp_node(const AdjParams& a, const double df[9],
     const double b_y = b_nu * nu * LN2;  // nu = 2^y
     const double w = b_y / ns.Gp;
     // dy = -(G_A dA + G_B dB + G_L0 dL0 + G_n dn) / G'
-    g_lnnu0 += w / LN2;  // L0 = log2 nu0, G_L0 = -1
+    constexpr double ILN2 = 1.0 / LN2;
+    g_lnnu0 += w * ILN2;  // L0 = log2 nu0, G_L0 = -1
     // At zero shear (possible only with n = 1, where no clamp is active) the
     // power law is singular in n and its one-sided limits sit on a clamp,
     // which does not depend on n at fixed nu0: no n or shear terms.
     if (ns.g2 > 0.0) {
       g_n += w * (a.log2c + 0.5 * log2(ns.g2));  // G_n = -log2(gamma*)
       if (ns.g2 > a.g2_floor) {
-        b_A += w * 0.5 * a.nm1 / (ns.g2 * LN2);
-        b_B += w * 0.5 * a.nm1 * ns.s * ns.s / (ns.g2 * LN2);
+        const double wg = w * 0.5 * a.nm1 * ILN2 / ns.g2;
+        b_A += wg;
+        b_B += wg * ns.s * ns.s;
       }
     }
   }
