@@ -62,6 +62,28 @@ struct Layout {
 #define PM_PAIR_STEP 1
 #endif
 
+// Rows per workgroup of the two-step kernel: the workgroups run in rounds of
+// PAIR_PER_CU per CU, so a last round that is mostly empty costs nearly a
+// full one; fewer rows recompute a larger share of halo rows (4 extra rows of
+// step k per workgroup).  Pick the row count in [PAIR_R_MIN, PAIR_R] that
+// minimises (rows + 4) / rows divided by the fraction of the last round used.
+int pair_rows_for(int nx, int ny, int cus) {
+  const int64_t strips = (nx + pm::PAIR_W - 1) / pm::PAIR_W, slots = (int64_t)pm::PAIR_PER_CU * cus;
+  int best = pm::PAIR_R;
+  double best_cost = 1e300;
+  for (int r = pm::PAIR_R; r >= pm::PAIR_R_MIN; --r) {
+    const int64_t wg = strips * ((ny + r - 1) / r);
+    const int64_t rounds = (wg + slots - 1) / slots;
+    const double fill = (double)wg / (double)(rounds * slots);
+    const double cost = (double)(r + 4) / r / fill;
+    if (cost < best_cost - 1e-12) {
+      best_cost = cost;
+      best = r;
+    }
+  }
+  return best;
+}
+
 bool pair_capable(const pm_params& p) {
   if (!PM_PAIR_STEP || p.dtype != PM_FP32 || p.periodic_x || p.periodic_y) return false;
   if (p.step_kernel == PM_STEP_PAIR) return true;
@@ -234,6 +256,7 @@ struct pm_ctx {
   pm::KParams<double> k64;
   pm::KParams<float> k32b;  // k32 on the second population region (two-step kernel)
   bool pair;                // two-step kernel available (FP32 cavity, second region)
+  int pair_rows;            // rows per workgroup of the two-step kernel
   pm::Launch launch;
   bool pow;
   hipGraphExec_t graph[2];  // chunk graphs starting at parity 0 / 1
@@ -279,8 +302,8 @@ hipError_t enqueue_steps(pm_ctx* c, hipStream_t s, int64_t k, int64_t start_step
   if (c->pair) {
     if ((start_steps & 1) && k > 0) e = single(t++);
     for (; e == hipSuccess && k - t >= 4; t += 4) {
-      e = pm::launch_step2(c->k32, c->k32b, s, c->pow, logda);
-      if (e == hipSuccess) e = pm::launch_step2(c->k32b, c->k32, s, c->pow, logda);
+      e = pm::launch_step2(c->k32, c->k32b, s, c->pow, logda, c->pair_rows);
+      if (e == hipSuccess) e = pm::launch_step2(c->k32b, c->k32, s, c->pow, logda, c->pair_rows);
     }
   }
   for (; e == hipSuccess && t < k; ++t) e = single(t);
@@ -409,6 +432,10 @@ int init_ctx(const pm_params* p, void* dev_ws, size_t ws_bytes, void* hip_stream
     c->k32b = c->k32;
     c->k32b.f = (float*)((char*)dev_ws + lay.off_pair + lay.off_f);
     c->k32b.g = (float*)((char*)dev_ws + lay.off_pair + lay.off_g);
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess || cus < 1)
+      cus = 256;
+    c->pair_rows = pair_rows_for(p->nx, p->ny, cus);
   }
   c->launch.stream = c->stream;
   c->launch.tiles_x = (p->nx + pm::TILE - 1) / pm::TILE;

@@ -96,11 +96,15 @@ constexpr int TILE = PM_TILE;   // nodes per workgroup (one row segment)
 // (three full rounds of 3 workgroups on each of 256 CUs; at 4096^2 it is 20%
 // faster per step than the single-step kernel, at 3072^2 and below equal or
 // slower).
+// PAIR_R is the nominal row count (the host tunes the actual one per grid
+// between PAIR_R_MIN and PAIR_R so that the workgroups fill whole rounds).
 #ifndef PM_PAIR_R
 #define PM_PAIR_R 24
 #endif
 constexpr int PAIR_W = PM_TILE - 4;
 constexpr int PAIR_R = PM_PAIR_R;
+constexpr int PAIR_R_MIN = 16;
+constexpr int PAIR_PER_CU = 3;  // resident workgroups per CU (LDS: 2 x 24 KB each)
 constexpr int64_t PAIR_MIN_WORKGROUPS = 9 * 256;
 constexpr int RED_BLOCKS = 1024; // partial-result slots of the residual
 
@@ -144,7 +148,7 @@ hipError_t launch_write_header(void* dst, int64_t steps, uint64_t tag, hipStream
 // Two time steps of an FP32 cavity (no periodic axis) in one pass, from the
 // natural-layout state in src (even step count) to dst.
 hipError_t launch_step2(const KParams<float>& src, const KParams<float>& dst, hipStream_t s, bool pow,
-                        bool logda);
+                        bool logda, int rows);
 hipError_t launch_stream_y(void* psi, int nx, int ny, double inv_L, int out_fp64, hipStream_t s);
 hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, hipStream_t s);
 

@@ -57,6 +57,8 @@ __global__ __launch_bounds__(TILE) void k_step_oop(KParams<T> src, KParams<T> ds
 //   B. row a - 1: pull f* from rows a - 2 .. a (walls: bounce-back, thermal
 //      anti-bounce-back), collide (step k + 1) -> f**;
 //   C. row a - 2: pull f** from rows a - 3 .. a - 1 -> S_{k+2}, store.
+// The number of rows per workgroup is chosen by the host (around 24: fewer
+// rows recompute more halo rows, more rows give fewer, longer workgroups).
 // Thread t works on column x0 - 2 + t, so step k covers two halo columns on
 // each side and step k + 1 one.  The populations that move along x go
 // through LDS rings of the last three rows; those that do not stay in the
@@ -108,14 +110,14 @@ __device__ __forceinline__ void pull_pair(const KParams<float>& p, float (*ring)
 }
 
 template <bool POW, bool LOGDA>
-__global__ __launch_bounds__(TILE) void k_step2(KParams<float> src, KParams<float> dst) {
+__global__ __launch_bounds__(TILE) void k_step2(KParams<float> src, KParams<float> dst, int rows) {
   __shared__ float ring1[3][NXS][TILE];  // f* of rows a - 2 .. a
   __shared__ float ring2[3][NXS][TILE];  // f** of rows a - 3 .. a - 1
   const int t = threadIdx.x;
-  const int x0 = blockIdx.x * PAIR_W, y0 = blockIdx.y * PAIR_R;
+  const int x0 = blockIdx.x * PAIR_W, y0 = blockIdx.y * rows;
   const int c = x0 - 2 + t;
   const bool col = c >= 0 && c < src.nx;
-  const int y_end = min(y0 + PAIR_R, src.ny);  // output rows [y0, y_end)
+  const int y_end = min(y0 + rows, src.ny);  // output rows [y0, y_end)
   Still r1m{}, r10{}, r1p{};  // f* of rows a - 2, a - 1, a (this column)
   Still r2m{}, r20{}, r2p{};  // f** of rows a - 3, a - 2, a - 1
   int s1 = 0;                 // slot of row a; rows a - 1, a - 2 in s1 - 1, s1 - 2 (mod 3)
@@ -453,14 +455,15 @@ hipError_t launch_step(const KParams<T>& p, const Launch& L, int parity, bool po
 }
 
 hipError_t launch_step2(const KParams<float>& src, const KParams<float>& dst, hipStream_t s, bool pow,
-                        bool logda) {
-  const dim3 grid((unsigned)((src.nx + PAIR_W - 1) / PAIR_W), (unsigned)((src.ny + PAIR_R - 1) / PAIR_R));
+                        bool logda, int rows) {
+  if (rows < 1) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((src.nx + PAIR_W - 1) / PAIR_W), (unsigned)((src.ny + rows - 1) / rows));
   if (pow) {
-    if (logda) hipLaunchKernelGGL((k_step2<true, true>), grid, dim3(TILE), 0, s, src, dst);
-    else hipLaunchKernelGGL((k_step2<true, false>), grid, dim3(TILE), 0, s, src, dst);
+    if (logda) hipLaunchKernelGGL((k_step2<true, true>), grid, dim3(TILE), 0, s, src, dst, rows);
+    else hipLaunchKernelGGL((k_step2<true, false>), grid, dim3(TILE), 0, s, src, dst, rows);
   } else {
-    if (logda) hipLaunchKernelGGL((k_step2<false, true>), grid, dim3(TILE), 0, s, src, dst);
-    else hipLaunchKernelGGL((k_step2<false, false>), grid, dim3(TILE), 0, s, src, dst);
+    if (logda) hipLaunchKernelGGL((k_step2<false, true>), grid, dim3(TILE), 0, s, src, dst, rows);
+    else hipLaunchKernelGGL((k_step2<false, false>), grid, dim3(TILE), 0, s, src, dst, rows);
   }
   return hipGetLastError();
 }
