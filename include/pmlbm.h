@@ -31,7 +31,9 @@
  *     failure of a call that had no context yet).
  *   - Device memory is always owned by the caller: the workspace passed to
  *     pm_init, and every output buffer.  The library allocates only its host
- *     context and (for pm_step) HIP graph objects, released by pm_destroy.
+ *     context, one private non-blocking stream on which pm_step captures its
+ *     HIP graphs, and those graphs, all released by pm_destroy (a sweep or
+ *     an adjoint likewise releases what it creates in its own destroy call).
  *   - A context is bound to the HIP stream given to pm_init; every call
  *     enqueues on that stream.  Calls that return host values (pm_nu,
  *     pm_residual, pm_run_to_steady) synchronise that stream.  A context is

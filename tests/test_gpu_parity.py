@@ -225,6 +225,36 @@ def test_full_size_4096_fp32_sampled():
     assert np.all(Ug[100:-100, 100:-100] == 0.0) and np.all(Tg[100:-100, 100:-100] == 0.5)
 
 
+def test_full_size_4096_fp32_random_state():
+    """The same 4096^2 workload and launch configuration, started from a random
+    non-equilibrium state so that every node moves and the viscosity solve
+    runs on the power-law branch everywhere: all fields, every node, against
+    the oracle after 5 steps (two-step passes, then one single step) and after
+    5 more (a single step, then two-step passes).  This covers every strip and
+    row-block edge of the two-step pass at the size it is timed at, including
+    the partial last strip and the partial last row block."""
+    kw = dict(n=0.8, Da=1e-2, Ra=1e5, Pr=10.0, eps=0.6)
+    N = 4096
+    f0, g0 = inputs.random_state(N, N, seed=11, amp=0.02, amp_T=0.1)
+    log("case: 4096^2 fp32 from a random state (seed 11)", kw)
+    cav = gpu_for(N, dtype="fp32", **kw)
+    cav.set_populations(torch.from_numpy(f0), torch.from_numpy(g0))
+    orc = oracle_for(N, **kw)
+    orc.set_state(f0, g0)
+    del f0, g0
+    for k in (5, 5):
+        cav.step(k)
+        orc.step(k)
+        Ug, Vg, Tg = gpu_fields(cav)
+        Ur, Vr, Tr = orc.fields()
+        errs = dict(U=rel_err(Ug, Ur), V=rel_err(Vg, Vr), theta=rel_err(Tg, Tr))
+        dnu = compare_nu(cav, orc)
+        log("  after", orc.steps, "steps:", errs, dnu)
+        assert max(errs.values()) <= 1e-4 and dnu <= 1e-4
+    del cav
+    torch.cuda.empty_cache()
+
+
 def test_stream_function():
     """psi from the GPU against its definition applied to the oracle's U
     (midpoint rule up each column, psi = 0 on the bottom wall), FP64; at the

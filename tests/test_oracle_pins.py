@@ -17,6 +17,7 @@ Flow (D2Q9 MRT, Eq. 12, halfway bounce-back walls):
     term's sign and magnitude and the eps factor of the force.
 Thermal (D2Q5 MRT, Eq. 18, anti-bounce-back Dirichlet walls):
   * Conduction: theta = 1 - x/N exactly, Nu = 1 (Eq. 24).
+  * Eq. (24) exact for theta quadratic in X with a wall slope varying in Y.
   * 1-D transient diffusion against its Fourier series.
   * Advection of a sine wave by a uniform flow (periodic box).
 Invariants: exact mass conservation; the discrete energy balance through the
@@ -217,6 +218,30 @@ def test_conduction_nusselt_is_one():
         x = (np.arange(N) + 0.5) / N
         assert np.abs(T - (1 - x)[None, :]).max() < 1e-12
         assert abs(o.nu_bar() - 1.0) < 1e-12
+
+
+def test_nusselt_is_exact_for_quadratic_temperature():
+    """Eq. (24) read as a one-sided second-order gradient through the wall
+    value and the first two nodes, averaged by the midpoint rule in Y: exact
+    for theta quadratic in X with a wall slope that varies along the wall.  (A
+    linear profile cannot tell this from a first-order gradient; the
+    curvature term b here can.)"""
+    N, ny = 24, 10
+    X = (np.arange(N) + 0.5) / N
+    Y = (np.arange(ny) + 0.5) / ny
+    a = -0.7 + 0.3 * np.cos(2 * math.pi * Y)  # wall slope d theta / dX at X = 0
+    b = 0.45
+    theta = 1.0 + a[:, None] * X[None, :] + b * X[None, :] ** 2
+    w9 = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+    w5 = np.array([1 / 3] + [1 / 6] * 4)
+    o = O.Oracle(O.lattice(N, ny, alpha=0.2))
+    f = np.broadcast_to(w9[:, None, None], (9, ny, N)).copy()
+    g = w5[:, None, None] * theta[None]
+    o.set_state(f, g)
+    assert abs(o.nu_bar() - 0.7) < 1e-13
+    # a first-order one-sided gradient would be off by b / (2 N)
+    first_order = np.mean((1.0 - theta[:, 0]) / (0.5 / N))
+    assert abs(first_order - 0.7) > 0.5 * b / (2 * N)
 
 
 def test_transient_diffusion_against_fourier_series():
