@@ -283,12 +283,41 @@ __device__ __forceinline__ void store_node(const KParams<T>& p, int i, int j, co
 // Then Newton steps, each clamped to [y_lo, y_hi] (iterates that leave the
 // range stay on the bound the root lies beyond).  The lanes of a wave loop
 // together until every lane has converged; a converged lane stops updating.
+// FP64 first takes the start and four Newton steps in FP32 on the hardware
+// exp2 / log2 / reciprocal (cheap, ~1e-6 in y), so that its own Newton steps,
+// whose library exp2 and log2 cost about 170 instructions each, converge in
+// two instead of four or five.
+constexpr int NU_FP32_STEPS = 4;
+
+template <typename T>
+__device__ __forceinline__ T nu_start(const KParams<T>& p, T A, T B) {
+  const T y = (p.lc0 + p.nm1 * (T(0.5) * flog2<T>(B) - T(1.584962500721156181453738943947816508))) * p.inv_n;
+  return fmin(fmax(y, p.y_lo), p.y_hi);  // log2(B = 0) = -inf: lands on a bound
+}
+
+template <>
+__device__ __forceinline__ double nu_start<double>(const KParams<double>& p, double A, double B) {
+  const float lo = (float)p.y_lo, hi = (float)p.y_hi, lc0 = (float)p.lc0, nm1 = (float)p.nm1;
+  const float Af = (float)A, Bf = (float)B;
+  float y = (lc0 + nm1 * (0.5f * __builtin_amdgcn_logf(Bf) - 1.5849625007f)) * (float)p.inv_n;
+  y = fminf(fmaxf(y, lo), hi);
+  for (int it = 0; it < NU_FP32_STEPS; ++it) {  // a fixed count: no lane depends on another
+    const float nu = __builtin_amdgcn_exp2f(y);
+    const float s = __builtin_amdgcn_rcpf(3.0f * nu + 0.5f);
+    const float g2 = Af + Bf * s * s;
+    const float G = (y - lc0) - 0.5f * nm1 * __builtin_amdgcn_logf(g2);
+    const float dG = 1.0f + 3.0f * nm1 * Bf * s * s * s * nu * __builtin_amdgcn_rcpf(g2);
+    const float yn = y - G * __builtin_amdgcn_rcpf(dG);
+    if (g2 > 0.0f && yn == yn) y = fminf(fmaxf(yn, lo), hi);  // no shear in FP32: the FP64 steps decide
+  }
+  return fmin(fmax((double)y, p.y_lo), p.y_hi);
+}
+
 template <typename T>
 __device__ __forceinline__ T solve_nu(const KParams<T>& p, T A, T B) {
   const T half = T(0.5);
   const T hn = half * p.nm1;
-  T y = (p.lc0 + p.nm1 * (half * flog2<T>(B) - T(1.584962500721156181453738943947816508))) * p.inv_n;
-  y = fmin(fmax(y, p.y_lo), p.y_hi);  // log2(B = 0) = -inf: lands on a bound
+  T y = nu_start<T>(p, A, B);
   bool conv = false;
   for (int it = 0; it < p.max_it; ++it) {
     const T nu = fexp2<T>(y);
