@@ -108,9 +108,9 @@ def sweep_main(args):
     cs = inputs.sweep_cases(0)
     cases = [dict(nx=c["N"], n=c["n"], Da=c["Da"], Ra=c["Ra"], Pr=10.0, eps=0.6, dtype=dt) for c in cs]
     log(f"sweep: {len(cases)} cases, sides {[c['N'] for c in cs]}, {dt}, tol {args.sweep_tol}")
-    order, times = P.tune(cases)
-    log(f"sweep: schedule {order} ({ {k: round(v, 1) for k, v in times.items()} } us/step)")
-    sw = P.Sweep(cases, order=order)
+    sched, times = P.tune(cases)
+    log(f"sweep: schedule {sched} ({ {k: round(v, 1) for k, v in times.items()} } us/step)")
+    sw = P.Sweep(cases, **sched)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     steps, res = sw.run(tol=args.sweep_tol, check_every=1000, max_steps=args.sweep_cap,
@@ -144,7 +144,8 @@ def sweep_main(args):
         "config": {"workload": "27-case sweep n in {0.6,0.8,1.0} x Da in {1e-3,1e-2,1e-1} x "
                                "Ra in {1e3,1e4,1e5}, eps=0.6, Pr=10, sides drawn from "
                                "{128,192,256,384,512} (seed 0)", "tol": args.sweep_tol,
-                   "check_every": 1000, "max_steps": args.sweep_cap, "schedule": order},
+                   "check_every": 1000, "max_steps": args.sweep_cap,
+                   "schedule": {"order": sched["order"], "tile": list(sched["tile"])}},
         "batched_s": round(t_batched, 3), "sequential_s": round(t_seq, 3),
         "sequential_cases_per_s": round(len(cases) / t_seq, 4),
         "speedup_vs_sequential": round(t_seq / t_batched, 3),

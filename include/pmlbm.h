@@ -197,7 +197,7 @@ int pm_copy_probe(const void* src, void* dst, size_t bytes, void* hip_stream);
 /* ---- Batched parameter sweep ----
  * Many independent cavities (e.g. the (n, Da, Ra) grid of the paper's
  * parametric study, Table 2, with uneven grid sides) advanced together: one
- * launch per time step covers every row tile of every case still running,
+ * launch per time step covers every tile of every case still running,
  * and a chunk of check_every steps plus the per-case residual test is
  * replayed as one HIP graph.  Each case stops at the first check with
  * residual < tol (or at max_steps, or on NaN/Inf) exactly as
@@ -222,6 +222,12 @@ int pm_sweep_create(const pm_params* cases, int ncases, void* dev_ws, size_t ws_
                     pm_sweep** out);
 /* Choose the tile schedule (PM_ORDER_*); used by the autotuner. */
 int pm_sweep_set_order(pm_sweep* s, int order);
+/* Choose the tile shape: one workgroup of tile_w * tile_h threads per tile of
+ * tile_w columns by tile_h rows of a case; tile_w in {64, 128, 256}, tile_h in
+ * {1, 2, 4}, tile_w * tile_h <= 256 (default 256 x 1).  Results are bitwise
+ * the same for every shape; used by the autotuner.  Synchronises the stream.
+ * PM_EINVAL for any other shape. */
+int pm_sweep_set_tile(pm_sweep* s, int tile_w, int tile_h);
 /* Run every live case until it stops (see above).  steps_out[i], r_out[i]
  * (arrays of ncases, may be NULL): steps taken and last residual of case i.
  * Returns PM_EDIVERGED if any case stopped on NaN/Inf. */

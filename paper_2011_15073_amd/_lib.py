@@ -26,7 +26,7 @@ EXPORTS = [
     "pm_set_logda", "pm_step", "pm_steps_done", "pm_nu", "pm_residual", "pm_run_to_steady",
     "pm_fields", "pm_stream_function", "pm_viscosity", "pm_get_populations", "pm_set_populations",
     "pm_state_bytes", "pm_save_state", "pm_load_state", "pm_copy_probe",
-    "pm_sweep_workspace_bytes", "pm_sweep_create", "pm_sweep_set_order", "pm_sweep_run",
+    "pm_sweep_workspace_bytes", "pm_sweep_create", "pm_sweep_set_order", "pm_sweep_set_tile", "pm_sweep_run",
     "pm_sweep_advance", "pm_sweep_status",
     "pm_sweep_step", "pm_sweep_case", "pm_sweep_destroy", "pm_sweep_last_error",
     "pm_adjoint_workspace_bytes", "pm_adjoint_create", "pm_adjoint_forward",
@@ -98,6 +98,7 @@ def _load():
         "pm_sweep_workspace_bytes": ([P(PmParams), i32, P(sz)], i32),
         "pm_sweep_create": ([P(PmParams), i32, vp, sz, vp, P(vp)], i32),
         "pm_sweep_set_order": ([vp, i32], i32),
+        "pm_sweep_set_tile": ([vp, i32, i32], i32),
         "pm_sweep_run": ([vp, dbl, i64, i64, P(i64), P(dbl)], i32),
         "pm_sweep_step": ([vp, i64], i32),
         "pm_sweep_advance": ([vp, dbl, i64, i64, i64, P(i32)], i32),

@@ -691,6 +691,7 @@ struct pm_sweep {
   std::vector<pm_ctx*> ctx;
   std::vector<int> ntiles, tile_base;
   int total_tiles;
+  int tile_w, tile_h;   // sweep tile: tile_w columns by tile_h rows (pm_sweep_set_tile)
   void* d_cases;        // SweepCase<T>[ncases]
   int2* d_sched;        // schedule entries (case, tile)
   int* d_live;          // 1 while the case still runs
@@ -744,7 +745,7 @@ int sweep_layout(const pm_params* cases, int n, SweepLayout& L, char* msg, size_
     L.off[i] = o;
     L.bytes[i] = layout_of(cases[i]).total;
     o = align_to(o + L.bytes[i], SWEEP_ALIGN);
-    tiles += ((cases[i].nx + pm::TILE - 1) / pm::TILE) * cases[i].ny;
+    tiles += ((cases[i].nx + 63) / 64) * cases[i].ny;  // the most tiles any tile shape gives (64 x 1)
   }
   const size_t case_sz = cases[0].dtype == PM_FP64 ? sizeof(pm::SweepCase<double>) : sizeof(pm::SweepCase<float>);
   L.off_cases = o;
@@ -797,20 +798,20 @@ hipError_t sweep_enqueue_chunk(pm_sweep* s, hipStream_t st, int64_t chunk, int p
     const int par = (int)((parity0 + t) & 1);
     if (s->dtype == PM_FP64)
       e = pm::launch_step_multi<double>((const pm::SweepCase<double>*)s->d_cases, s->d_sched, s->d_live,
-                                        s->total_tiles, par, st);
+                                        s->total_tiles, par, s->tile_w, s->tile_h, st);
     else
       e = pm::launch_step_multi<float>((const pm::SweepCase<float>*)s->d_cases, s->d_sched, s->d_live,
-                                       s->total_tiles, par, st);
+                                       s->total_tiles, par, s->tile_w, s->tile_h, st);
   }
   if (e != hipSuccess) return e;
   const int par_end = (int)((parity0 + chunk) & 1);
   if (s->dtype == PM_FP64)
     return pm::launch_resid_multi<double>((const pm::SweepCase<double>*)s->d_cases, s->ncases, s->d_sched,
-                                          s->d_live, s->total_tiles, par_end, s->d_partial, s->d_st, chunk,
-                                          tol, max_steps, st);
+                                          s->d_live, s->total_tiles, par_end, s->tile_w, s->tile_h,
+                                          s->d_partial, s->d_st, chunk, tol, max_steps, st);
   return pm::launch_resid_multi<float>((const pm::SweepCase<float>*)s->d_cases, s->ncases, s->d_sched,
-                                       s->d_live, s->total_tiles, par_end, s->d_partial, s->d_st, chunk, tol,
-                                       max_steps, st);
+                                       s->d_live, s->total_tiles, par_end, s->tile_w, s->tile_h, s->d_partial,
+                                       s->d_st, chunk, tol, max_steps, st);
 }
 
 void sweep_drop_graphs(pm_sweep* s) {
@@ -857,11 +858,26 @@ void fill_case(pm_sweep* s, int i, pm_ctx* c) {
   pm::SweepCase<T> sc{};
   sc.p = kparams_of<T>(c);
   sc.snap = (T*)((char*)c->ws + c->lay.off_snap);
-  sc.tiles_x = c->launch.tiles_x;
-  sc.ntiles = c->launch.ntiles;
+  sc.tiles_x = (c->p.nx + s->tile_w - 1) / s->tile_w;
+  sc.ntiles = s->ntiles[i];
   sc.tile_base = s->tile_base[i];
   sc.pow = c->pow ? 1 : 0;
   memcpy(s->h_cases.data() + i * sizeof(sc), &sc, sizeof(sc));
+}
+
+// Tile counts, the case table and the schedule for the current tile shape.
+void sweep_retile(pm_sweep* s) {
+  int tb = 0;
+  for (int i = 0; i < s->ncases; ++i) {
+    const pm_params& p = s->ctx[i]->p;
+    s->ntiles[i] = ((p.nx + s->tile_w - 1) / s->tile_w) * ((p.ny + s->tile_h - 1) / s->tile_h);
+    s->tile_base[i] = tb;
+    tb += s->ntiles[i];
+    if (s->dtype == PM_FP64) fill_case<double>(s, i, s->ctx[i]);
+    else fill_case<float>(s, i, s->ctx[i]);
+  }
+  s->total_tiles = tb;
+  build_schedule(s);
 }
 
 }  // namespace
@@ -906,7 +922,8 @@ int pm_sweep_create(const pm_params* cases, int ncases, void* dev_ws, size_t ws_
   s->dtype = cases[0].dtype;
   s->order = PM_ORDER_CASE;
   s->stream = (hipStream_t)hip_stream;
-  s->total_tiles = L.total_tiles;
+  s->tile_w = pm::TILE;
+  s->tile_h = 1;
   char* base = (char*)dev_ws;
   s->d_cases = base + L.off_cases;
   s->d_sched = (int2*)(base + L.off_sched);
@@ -919,7 +936,6 @@ int pm_sweep_create(const pm_params* cases, int ncases, void* dev_ws, size_t ws_
   s->tile_base.resize(ncases);
   const size_t case_sz = s->dtype == PM_FP64 ? sizeof(pm::SweepCase<double>) : sizeof(pm::SweepCase<float>);
   s->h_cases.assign(ncases * case_sz, 0);
-  int tb = 0;
   for (int i = 0; i < ncases; ++i) {
     rc = init_ctx(&cases[i], base + L.off[i], L.bytes[i], hip_stream, false, &s->ctx[i]);
     if (rc) {
@@ -928,13 +944,8 @@ int pm_sweep_create(const pm_params* cases, int ncases, void* dev_ws, size_t ws_
       pm_sweep_destroy(s);
       return rc;
     }
-    s->ntiles[i] = s->ctx[i]->launch.ntiles;
-    s->tile_base[i] = tb;
-    tb += s->ntiles[i];
-    if (s->dtype == PM_FP64) fill_case<double>(s, i, s->ctx[i]);
-    else fill_case<float>(s, i, s->ctx[i]);
   }
-  build_schedule(s);
+  sweep_retile(s);
   s->h_live.assign(ncases, 1);
   s->h_st.assign(ncases, pm::SweepStatus{0, INFINITY});
   hipError_t e = hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking);
@@ -969,6 +980,27 @@ int pm_sweep_set_order(pm_sweep* s, int order) {
                                 hipMemcpyHostToDevice, s->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   if (e != hipSuccess) return sweep_fail(s, PM_EDEVICE, "pm_sweep_set_order: %s", hipGetErrorString(e));
+  return PM_OK;
+}
+
+int pm_sweep_set_tile(pm_sweep* s, int tile_w, int tile_h) {
+  if (!s) return PM_EINVAL;
+  if (!pm::sweep_tile_ok(tile_w, tile_h))
+    return sweep_fail(s, PM_EINVAL, "pm_sweep_set_tile: %d x %d is not a supported tile (width 64, 128 or 256, "
+                      "height 1, 2 or 4, at most %d threads)", tile_w, tile_h, pm::TILE);
+  // the previous tile shape's launches may still read the case table
+  hipError_t e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return sweep_fail(s, PM_EDEVICE, "pm_sweep_set_tile: %s", hipGetErrorString(e));
+  s->tile_w = tile_w;
+  s->tile_h = tile_h;
+  sweep_retile(s);
+  sweep_drop_graphs(s);
+  e = hipMemcpyAsync(s->d_cases, s->h_cases.data(), s->h_cases.size(), hipMemcpyHostToDevice, s->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(s->d_sched, s->h_sched.data(), s->h_sched.size() * sizeof(int2), hipMemcpyHostToDevice,
+                       s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return sweep_fail(s, PM_EDEVICE, "pm_sweep_set_tile: %s", hipGetErrorString(e));
   return PM_OK;
 }
 
@@ -1032,10 +1064,10 @@ int pm_sweep_step(pm_sweep* s, int64_t k) {
     const int par = (int)((s->gsteps + t) & 1);
     if (s->dtype == PM_FP64)
       e = pm::launch_step_multi<double>((const pm::SweepCase<double>*)s->d_cases, s->d_sched, s->d_live,
-                                        s->total_tiles, par, s->stream);
+                                        s->total_tiles, par, s->tile_w, s->tile_h, s->stream);
     else
       e = pm::launch_step_multi<float>((const pm::SweepCase<float>*)s->d_cases, s->d_sched, s->d_live,
-                                       s->total_tiles, par, s->stream);
+                                       s->total_tiles, par, s->tile_w, s->tile_h, s->stream);
   }
   if (e != hipSuccess) return sweep_fail(s, PM_EDEVICE, "pm_sweep_step: %s", hipGetErrorString(e));
   // live cases advance together; the per-case counters follow on the device

@@ -477,13 +477,14 @@ __device__ __forceinline__ void collide(const KParams<T>& p, int k, T df[9], T d
 // update written to another buffer, which then holds the complete next
 // state because every slot is written exactly once per step).
 template <typename T, bool ODD, bool POW, bool LOGDA>
-__device__ __forceinline__ void step_tile(const KParams<T>& p, const KParams<T>& d, int i0, int j) {
-  const int i = i0 + threadIdx.x;
+__device__ __forceinline__ void step_tile(const KParams<T>& p, const KParams<T>& d, int i0, int j, int lx) {
+  const int i = i0 + lx;
   T df[9], dg[5];
   if (ODD) {
     // Waves whose 64 nodes all have their 8 neighbours inside the grid take
-    // the branch-free interior path (wave-uniform test).
-    const int w0 = i0 + (__builtin_amdgcn_readfirstlane(threadIdx.x) & ~63);
+    // the branch-free interior path (wave-uniform test; a wave covers 64
+    // consecutive columns of row j starting at a multiple of 64 in lx).
+    const int w0 = i0 + (__builtin_amdgcn_readfirstlane(lx) & ~63);
     const bool interior = w0 >= 1 && w0 + 63 <= p.nx - 2 && j >= 1 && j <= p.ny - 2;
     if (interior) {
       load_interior_odd<T>(p, row_base(p, j), i, df, dg);

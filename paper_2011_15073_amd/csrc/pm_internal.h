@@ -52,8 +52,8 @@ template <typename T>
 struct SweepCase {
   KParams<T> p;
   T* snap;       // residual snapshot of theta (shifted)
-  int tiles_x;   // row tiles per row
-  int ntiles;    // tiles of this case
+  int tiles_x;   // tiles across a row of the grid: ceil(nx / tile width)
+  int ntiles;    // tiles of this case: tiles_x * ceil(ny / tile height)
   int tile_base; // first slot of this case in the case-major per-tile arrays
   int pow;       // n != 1: solve the power-law viscosity
 };
@@ -133,12 +133,17 @@ hipError_t launch_set_pop(const KParams<T>& p, const Launch& L, const void* f, c
 template <typename T>
 hipError_t launch_set_logda(const KParams<T>& p, const Launch& L, T* dst, const void* src,
                             int in_fp64);
+// Sweep tiles are tw columns by th rows: tw in {64, 128, 256}, th in {1, 2, 4},
+// tw * th <= TILE threads (a wave then lies within one grid row).
+inline bool sweep_tile_ok(int tw, int th) {
+  return (tw == 64 || tw == 128 || tw == 256) && (th == 1 || th == 2 || th == 4) && tw * th <= TILE;
+}
 template <typename T>
 hipError_t launch_step_multi(const SweepCase<T>* cases, const int2* sched, const int* live,
-                             int nsched, int parity, hipStream_t s);
+                             int nsched, int parity, int tw, int th, hipStream_t s);
 template <typename T>
 hipError_t launch_resid_multi(const SweepCase<T>* cases, int ncases, const int2* sched, int* live,
-                              int nsched, int parity, double* partial, SweepStatus* st,
+                              int nsched, int parity, int tw, int th, double* partial, SweepStatus* st,
                               int64_t chunk, double tol, int64_t max_steps, hipStream_t s);
 template <typename S>
 hipError_t launch_adjoint(const KParams<S>& st, const AdjParams& a, int parity, const double* lam_next,

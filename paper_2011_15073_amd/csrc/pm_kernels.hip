@@ -37,7 +37,7 @@ template <typename T, bool ODD, bool POW, bool LOGDA>
 __global__ __launch_bounds__(TILE) void k_step(KParams<T> p, int tiles_x, int ntiles) {
   const int tile = tile_of_block(blockIdx.x, ntiles);
   const int j = tile / tiles_x;
-  step_tile<T, ODD, POW, LOGDA>(p, p, (tile - j * tiles_x) * TILE, j);
+  step_tile<T, ODD, POW, LOGDA>(p, p, (tile - j * tiles_x) * TILE, j, threadIdx.x);
 }
 
 // The same step, read from state src and written to state dst (another
@@ -45,7 +45,7 @@ __global__ __launch_bounds__(TILE) void k_step(KParams<T> p, int tiles_x, int nt
 template <typename T, bool ODD, bool POW, bool LOGDA>
 __global__ __launch_bounds__(TILE) void k_step_oop(KParams<T> src, KParams<T> dst, int tiles_x) {
   const int j = blockIdx.x / tiles_x;
-  step_tile<T, ODD, POW, LOGDA>(src, dst, (blockIdx.x - j * tiles_x) * TILE, j);
+  step_tile<T, ODD, POW, LOGDA>(src, dst, (blockIdx.x - j * tiles_x) * TILE, j, threadIdx.x);
 }
 
 // ---- two time steps in one pass (FP32, cavity walls) ----
@@ -168,20 +168,25 @@ __global__ __launch_bounds__(TILE) void k_step2(KParams<float> src, KParams<floa
 
 // ---- batched parameter sweep: one launch steps every live case ----
 // Workgroup b takes the (case, tile) pair of entry b of the schedule; cases
-// that have met their stopping test are skipped.  Each case runs the same
-// tile body as the single-case kernel, so a case advanced here is bitwise
-// identical to the same case advanced alone.
+// that have met their stopping test are skipped.  A tile is tw columns by th
+// rows (tw a multiple of 64, tw * th threads): thread t works on column
+// t % tw, row t / tw of the tile, so every wave lies within one grid row.
+// Each case runs the same per-node body as the single-case kernel, so a case
+// advanced here is bitwise identical to the same case advanced alone,
+// whatever the tile shape.
 template <typename T, bool ODD>
 __global__ __launch_bounds__(TILE) void k_step_multi(const SweepCase<T>* __restrict__ cases,
                                                      const int2* __restrict__ sched,
-                                                     const int* __restrict__ live) {
+                                                     const int* __restrict__ live, int tw, int th) {
   const int2 e = sched[blockIdx.x];  // (case, tile within the case)
   if (!live[e.x]) return;
   const SweepCase<T>& c = cases[e.x];
-  const int j = e.y / c.tiles_x;
-  const int i0 = (e.y - j * c.tiles_x) * TILE;
-  if (c.pow) step_tile<T, ODD, true, false>(c.p, c.p, i0, j);
-  else step_tile<T, ODD, false, false>(c.p, c.p, i0, j);
+  const int ty = e.y / c.tiles_x;
+  const int lx = (int)threadIdx.x % tw, j = ty * th + (int)threadIdx.x / tw;
+  if (j >= c.p.ny) return;  // whole waves
+  const int i0 = (e.y - ty * c.tiles_x) * tw;
+  if (c.pow) step_tile<T, ODD, true, false>(c.p, c.p, i0, j, lx);
+  else step_tile<T, ODD, false, false>(c.p, c.p, i0, j, lx);
 }
 
 // Rest state: df = 0, dg_q = w_q (T_init - T_ref).  (The padding of the
@@ -273,22 +278,23 @@ __global__ __launch_bounds__(256) void k_max_final(const double* partial, int n,
   if (threadIdx.x == 0) out[0] = red[0];
 }
 
-// Sweep residual: one workgroup per schedule entry (a row tile of a live
-// case) -> max |theta - snapshot| over the tile into the tile's slot of the
-// case-major partial array, snapshot := theta.
+// Sweep residual: one workgroup per schedule entry (a tile of a live case,
+// laid out as in k_step_multi) -> max |theta - snapshot| over the tile into
+// the tile's slot of the case-major partial array, snapshot := theta.
 template <typename T>
 __global__ __launch_bounds__(TILE) void k_resid_multi(const SweepCase<T>* __restrict__ cases,
                                                       const int2* __restrict__ sched,
                                                       const int* __restrict__ live, int parity,
-                                                      double* __restrict__ partial) {
+                                                      double* __restrict__ partial, int tw, int th) {
   __shared__ double red[TILE];
   const int2 e = sched[blockIdx.x];
   if (!live[e.x]) return;  // uniform over the workgroup
   const SweepCase<T>& c = cases[e.x];
-  const int j = e.y / c.tiles_x;
-  const int i = (e.y - j * c.tiles_x) * TILE + threadIdx.x;
+  const int ty = e.y / c.tiles_x;
+  const int j = ty * th + (int)threadIdx.x / tw;
+  const int i = (e.y - ty * c.tiles_x) * tw + (int)threadIdx.x % tw;
   double mx = 0.0;
-  if (i < c.p.nx) {
+  if (i < c.p.nx && j < c.p.ny) {
     T g[5];
     if (parity) load_g<T, true>(c.p, i, j, g); else load_g<T, false>(c.p, i, j, g);
     const T dT = g[0] + ((g[1] + g[2]) + (g[3] + g[4]));
@@ -300,7 +306,7 @@ __global__ __launch_bounds__(TILE) void k_resid_multi(const SweepCase<T>* __rest
   }
   red[threadIdx.x] = mx;
   __syncthreads();
-  for (int s = TILE / 2; s > 0; s >>= 1) {
+  for (int s = (int)blockDim.x / 2; s > 0; s >>= 1) {  // blockDim.x = tw * th, a power of two
     if ((int)threadIdx.x < s) {
       const double o = red[threadIdx.x + s];
       red[threadIdx.x] = o > red[threadIdx.x] ? o : red[threadIdx.x];
@@ -487,20 +493,22 @@ hipError_t launch_step_oop(const KParams<T>& src, const KParams<T>& dst, const L
 
 template <typename T>
 hipError_t launch_step_multi(const SweepCase<T>* cases, const int2* sched, const int* live,
-                             int nsched, int parity, hipStream_t s) {
+                             int nsched, int parity, int tw, int th, hipStream_t s) {
+  if (!sweep_tile_ok(tw, th)) return hipErrorInvalidValue;
   if (parity)
-    hipLaunchKernelGGL((k_step_multi<T, true>), dim3(nsched), dim3(TILE), 0, s, cases, sched, live);
+    hipLaunchKernelGGL((k_step_multi<T, true>), dim3(nsched), dim3(tw * th), 0, s, cases, sched, live, tw, th);
   else
-    hipLaunchKernelGGL((k_step_multi<T, false>), dim3(nsched), dim3(TILE), 0, s, cases, sched, live);
+    hipLaunchKernelGGL((k_step_multi<T, false>), dim3(nsched), dim3(tw * th), 0, s, cases, sched, live, tw, th);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_resid_multi(const SweepCase<T>* cases, int ncases, const int2* sched, int* live,
-                              int nsched, int parity, double* partial, SweepStatus* st,
+                              int nsched, int parity, int tw, int th, double* partial, SweepStatus* st,
                               int64_t chunk, double tol, int64_t max_steps, hipStream_t s) {
-  hipLaunchKernelGGL((k_resid_multi<T>), dim3(nsched), dim3(TILE), 0, s, cases, sched,
-                     (const int*)live, parity, partial);
+  if (!sweep_tile_ok(tw, th)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_resid_multi<T>), dim3(nsched), dim3(tw * th), 0, s, cases, sched,
+                     (const int*)live, parity, partial, tw, th);
   hipLaunchKernelGGL((k_retire<T>), dim3(1), dim3(64), 0, s, cases, ncases, (const double*)partial,
                      live, st, chunk, tol, max_steps);
   return hipGetLastError();
@@ -626,10 +634,10 @@ hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, hipStream
                                         const void*, int);                                      \
   template hipError_t launch_set_logda<T>(const KParams<T>&, const Launch&, T*, const void*, int); \
   template hipError_t launch_step_multi<T>(const SweepCase<T>*, const int2*, const int*, int, int, \
-                                           hipStream_t);                                          \
+                                           int, int, hipStream_t);                                \
   template hipError_t launch_resid_multi<T>(const SweepCase<T>*, int, const int2*, int*, int, int, \
-                                            double*, SweepStatus*, int64_t, double, int64_t,      \
-                                            hipStream_t);
+                                            int, int, double*, SweepStatus*, int64_t, double,     \
+                                            int64_t, hipStream_t);
 PM_INST(float)
 PM_INST(double)
 #undef PM_INST

@@ -6,9 +6,11 @@ launch per time step over all live cases and one HIP-graph replay per chunk
 of steps plus the per-case stopping test.  Each case ends bitwise equal to
 the same case run alone with ``Cavity.run_to_steady``.
 
-The tuner times each tile schedule (PM_ORDER_*) on a scratch sweep of the
-same case set and caches the fastest in a JSON file keyed by the device and
-the case shapes (``$PMLBM_TUNE_CACHE``, default ``~/.cache/pmlbm/sweep.json``).
+The tuner times every tile order (PM_ORDER_*) with every tile shape (tile_w
+columns by tile_h rows per workgroup) on a scratch sweep of the same case set
+and caches the fastest in a JSON file keyed by the device and the case shapes
+(``$PMLBM_TUNE_CACHE``, default ``~/.cache/pmlbm/sweep.json``).  Results do
+not depend on the schedule: every choice gives bitwise the same cases.
 """
 import ctypes as C
 import hashlib
@@ -23,6 +25,8 @@ from .cavity import _TORCH_DT
 
 ORDERS = {"case": _lib.PM_ORDER_CASE, "largest": _lib.PM_ORDER_LARGEST,
           "interleave": _lib.PM_ORDER_INTERLEAVE}
+# tile shapes (columns, rows) the sweep kernels take
+TILES = [(256, 1), (128, 2), (64, 4), (128, 1), (64, 2), (64, 1)]
 
 
 class _CaseView:
@@ -71,7 +75,7 @@ class Sweep:
     """``cases``: list of dicts of ``make_params`` keywords, each with ``nx``
     (and optionally ``ny``)."""
 
-    def __init__(self, cases, *, device="cuda:0", order="case"):
+    def __init__(self, cases, *, device="cuda:0", order="case", tile=(256, 1)):
         self.device = torch.device(device)
         n = len(cases)
         arr = (_lib.PmParams * n)()
@@ -94,6 +98,7 @@ class Sweep:
                                       C.byref(h)))
         self._h = h
         self.set_order(order)
+        self.set_tile(*tile)
 
     def _check(self, rc):
         return check(rc, self._h, lib.pm_sweep_last_error)
@@ -101,6 +106,10 @@ class Sweep:
     def set_order(self, order):
         self.order = order
         self._check(lib.pm_sweep_set_order(self._h, ORDERS[order]))
+
+    def set_tile(self, tile_w, tile_h=1):
+        self.tile = (int(tile_w), int(tile_h))
+        self._check(lib.pm_sweep_set_tile(self._h, int(tile_w), int(tile_h)))
 
     def step(self, k):
         self._check(lib.pm_sweep_step(self._h, int(k)))
@@ -149,8 +158,9 @@ def _key(cases, device):
 
 
 def tune(cases, *, device="cuda:0", steps=200, use_cache=True):
-    """Fastest schedule order for this case set: cached, else timed on a
-    scratch sweep (``steps`` steps per order after a warm-up)."""
+    """Fastest schedule for this case set: cached, else timed on a scratch
+    sweep (``steps`` steps per tile order and tile shape, after a warm-up).
+    Returns ({"order": ..., "tile": (tile_w, tile_h)}, {"order WxH": us/step})."""
     key = _key(cases, torch.device(device))
     path = _cache_path()
     cache = {}
@@ -159,25 +169,30 @@ def tune(cases, *, device="cuda:0", steps=200, use_cache=True):
             cache = json.load(open(path))
         except (OSError, ValueError):
             cache = {}
-        if key in cache:
-            return cache[key]["order"], cache[key]["us_per_step"]
+        hit = cache.get(key)
+        if hit and "tile" in hit:
+            return {"order": hit["order"], "tile": tuple(hit["tile"])}, hit["us_per_step"]
     scratch = Sweep(cases, device=device)
-    times = {}
-    for name in ORDERS:
-        scratch.set_order(name)
-        scratch.step(20)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(scratch.stream)
-        scratch.step(steps)
-        e1.record(scratch.stream)
-        e1.synchronize()
-        times[name] = e0.elapsed_time(e1) * 1e3 / steps
+    times, best, best_t = {}, None, float("inf")
+    for tile in TILES:
+        scratch.set_tile(*tile)
+        for name in ORDERS:
+            scratch.set_order(name)
+            scratch.step(20)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(scratch.stream)
+            scratch.step(steps)
+            e1.record(scratch.stream)
+            e1.synchronize()
+            t = e0.elapsed_time(e1) * 1e3 / steps
+            times[f"{name} {tile[0]}x{tile[1]}"] = t
+            if t < best_t:
+                best, best_t = {"order": name, "tile": tile}, t
     scratch.close()
     del scratch
-    best = min(times, key=times.get)
     if use_cache:
-        cache[key] = {"order": best, "us_per_step": times}
+        cache[key] = {"order": best["order"], "tile": list(best["tile"]), "us_per_step": times}
         try:
             os.makedirs(os.path.dirname(path), exist_ok=True)
             json.dump(cache, open(path, "w"), indent=1)

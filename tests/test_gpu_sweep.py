@@ -80,14 +80,42 @@ def test_sweep_case_matches_oracle():
     assert abs(view.nu() - orc.nu_bar()) / orc.nu_bar() <= 1e-11
 
 
-def test_tuner_returns_a_valid_order(tmp_path, monkeypatch):
+def test_tuner_returns_a_valid_schedule(tmp_path, monkeypatch):
     monkeypatch.setenv("PMLBM_TUNE_CACHE", str(tmp_path / "tune.json"))
     cases = [dict(c, dtype="fp32") for c in CASES]
-    order, times = P.tune(cases, steps=50)
-    assert order in ("case", "largest", "interleave")
-    assert all(t > 0 for t in times.values())
-    order2, _ = P.tune(cases, steps=50)  # served from the cache
-    assert order2 == order
+    best, times = P.tune(cases, steps=50)
+    assert best["order"] in ("case", "largest", "interleave")
+    assert best["tile"] in P.sweep.TILES
+    assert len(times) == 3 * len(P.sweep.TILES) and all(t > 0 for t in times.values())
+    best2, _ = P.tune(cases, steps=50)  # served from the cache
+    assert best2 == best
+    sw = P.Sweep(cases, **best)
+    assert sw.tile == best["tile"]
+
+
+@pytest.mark.parametrize("dtype", ["fp32", "fp64"])
+@pytest.mark.parametrize("tile", [(128, 2), (64, 4), (64, 1)])
+def test_tile_shape_does_not_change_results(dtype, tile):
+    """Every tile shape gives the same stopping steps, residuals and
+    populations as the default 256 x 1 tiles (ragged sides, a 70-row case)."""
+    cases = [dict(c, dtype=dtype) for c in CASES]
+    ref = P.Sweep(cases)
+    s_ref, r_ref = ref.run(tol=TOL, check_every=CHECK, max_steps=CAP)
+    sw = P.Sweep(cases, order="interleave", tile=tile)
+    steps, res = sw.run(tol=TOL, check_every=CHECK, max_steps=CAP)
+    assert steps == s_ref and res == r_ref
+    dt = torch.float64 if dtype == "fp64" else torch.float32
+    for i in range(len(cases)):
+        fa, ga = ref.case(i).populations(dt)
+        fb, gb = sw.case(i).populations(dt)
+        assert torch.equal(fa, fb) and torch.equal(ga, gb), i
+
+
+def test_unsupported_tile_shape_is_rejected():
+    sw = P.Sweep([dict(CASES[0], dtype="fp32")])
+    for bad in ((32, 1), (256, 2), (96, 1), (64, 3)):
+        with pytest.raises(Exception):
+            sw.set_tile(*bad)
 
 
 SWEEP27_ORACLE = {}
