@@ -220,7 +220,7 @@ int pm_sweep_workspace_bytes(const pm_params* cases, int ncases, size_t* bytes);
  * Synchronises the stream. */
 int pm_sweep_create(const pm_params* cases, int ncases, void* dev_ws, size_t ws_bytes, void* hip_stream,
                     pm_sweep** out);
-/* Choose the tile schedule (PM_ORDER_*); used by the autotuner. */
+/* Choose the tile order (PM_ORDER_*); used by the autotuner. */
 int pm_sweep_set_order(pm_sweep* s, int order);
 /* Choose the tile shape: one workgroup of tile_w * tile_h threads per tile of
  * tile_w columns by tile_h rows of a case; tile_w in {64, 128, 256}, tile_h in
