@@ -62,6 +62,16 @@ struct Layout {
 #define PM_PAIR_STEP 1
 #endif
 
+// Row-segment width of the single-step kernels' workgroups (64, 128 or 256
+// nodes; one lane per node either way, so the results do not depend on it).
+// Measured on one MI355X (us per step, widths 256 / 128 / 64):
+//   FP64 512^2 15.2 / 15.2 / 14.0, 1024^2 44.8 / 44.9 / 45.8, 4096^2 637 / 615 / 634;
+//   FP32 512^2 8.3 / 8.3 / 7.5, 1024^2 21.2 / 22.1 / 23.6, 2048^2 73.0 / 76.9 / 84.1.
+int step_width_for(int nx, int ny, int dtype) {
+  if ((int64_t)nx * ny <= 512 * 512) return 64;
+  return dtype == PM_FP64 ? 128 : 256;
+}
+
 // Rows per workgroup of the two-step kernel: the workgroups run in rounds of
 // PAIR_PER_CU per CU, so a last round that is mostly empty costs nearly a
 // full one; fewer rows recompute a larger share of halo rows (4 extra rows of
@@ -440,6 +450,9 @@ int init_ctx(const pm_params* p, void* dev_ws, size_t ws_bytes, void* hip_stream
   c->launch.stream = c->stream;
   c->launch.tiles_x = (p->nx + pm::TILE - 1) / pm::TILE;
   c->launch.ntiles = c->launch.tiles_x * p->ny;
+  c->launch.step_w = std::min(step_width_for(p->nx, p->ny, p->dtype), pm::TILE);
+  c->launch.step_tiles_x = (p->nx + c->launch.step_w - 1) / c->launch.step_w;
+  c->launch.step_ntiles = c->launch.step_tiles_x * p->ny;
   c->red = (double*)((char*)dev_ws + lay.off_red);
   hipError_t e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
   if (e != hipSuccess) {

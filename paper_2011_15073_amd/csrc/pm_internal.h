@@ -80,8 +80,11 @@ struct AdjParams {
 
 struct Launch {
   hipStream_t stream;
-  int tiles_x;     // row tiles of TILE nodes
-  int ntiles;      // tiles_x * ny
+  int tiles_x;       // row tiles of TILE nodes
+  int ntiles;        // tiles_x * ny
+  int step_w;        // row-segment width of the step kernels' workgroups (64, 128 or 256)
+  int step_tiles_x;  // ceil(nx / step_w)
+  int step_ntiles;   // step_tiles_x * ny
 };
 
 #ifndef PM_TILE

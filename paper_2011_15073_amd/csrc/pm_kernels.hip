@@ -33,11 +33,12 @@ namespace {
 
 using namespace pm::dev;
 
+// One workgroup per row segment of blockDim.x nodes (64, 128 or 256).
 template <typename T, bool ODD, bool POW, bool LOGDA>
 __global__ __launch_bounds__(TILE) void k_step(KParams<T> p, int tiles_x, int ntiles) {
   const int tile = tile_of_block(blockIdx.x, ntiles);
   const int j = tile / tiles_x;
-  step_tile<T, ODD, POW, LOGDA>(p, p, (tile - j * tiles_x) * TILE, j, threadIdx.x);
+  step_tile<T, ODD, POW, LOGDA>(p, p, (tile - j * tiles_x) * (int)blockDim.x, j, threadIdx.x);
 }
 
 // The same step, read from state src and written to state dst (another
@@ -45,7 +46,7 @@ __global__ __launch_bounds__(TILE) void k_step(KParams<T> p, int tiles_x, int nt
 template <typename T, bool ODD, bool POW, bool LOGDA>
 __global__ __launch_bounds__(TILE) void k_step_oop(KParams<T> src, KParams<T> dst, int tiles_x) {
   const int j = blockIdx.x / tiles_x;
-  step_tile<T, ODD, POW, LOGDA>(src, dst, (blockIdx.x - j * tiles_x) * TILE, j, threadIdx.x);
+  step_tile<T, ODD, POW, LOGDA>(src, dst, (blockIdx.x - j * tiles_x) * (int)blockDim.x, j, threadIdx.x);
 }
 
 // ---- two time steps in one pass (FP32, cavity walls) ----
@@ -446,9 +447,10 @@ inline int grid_for(int64_t n, int per = 256, int cap = 65536) {
 
 template <typename T>
 hipError_t launch_step(const KParams<T>& p, const Launch& L, int parity, bool pow, bool logda) {
-  dim3 grid(L.ntiles), block(TILE);
+  if (!(L.step_w == 64 || L.step_w == 128 || L.step_w == 256) || L.step_w > TILE) return hipErrorInvalidValue;
+  dim3 grid(L.step_ntiles), block(L.step_w);
 #define PM_STEP(ODD, POW, LOG) \
-  hipLaunchKernelGGL((k_step<T, ODD, POW, LOG>), grid, block, 0, L.stream, p, L.tiles_x, L.ntiles)
+  hipLaunchKernelGGL((k_step<T, ODD, POW, LOG>), grid, block, 0, L.stream, p, L.step_tiles_x, L.step_ntiles)
   if (parity) {
     if (pow) { if (logda) PM_STEP(true, true, true); else PM_STEP(true, true, false); }
     else { if (logda) PM_STEP(true, false, true); else PM_STEP(true, false, false); }
@@ -477,9 +479,10 @@ hipError_t launch_step2(const KParams<float>& src, const KParams<float>& dst, hi
 template <typename T>
 hipError_t launch_step_oop(const KParams<T>& src, const KParams<T>& dst, const Launch& L, int parity,
                            bool pow, bool logda) {
-  dim3 grid(L.ntiles), block(TILE);
+  if (!(L.step_w == 64 || L.step_w == 128 || L.step_w == 256) || L.step_w > TILE) return hipErrorInvalidValue;
+  dim3 grid(L.step_ntiles), block(L.step_w);
 #define PM_OOP(ODD, POW, LOG) \
-  hipLaunchKernelGGL((k_step_oop<T, ODD, POW, LOG>), grid, block, 0, L.stream, src, dst, L.tiles_x)
+  hipLaunchKernelGGL((k_step_oop<T, ODD, POW, LOG>), grid, block, 0, L.stream, src, dst, L.step_tiles_x)
   if (parity) {
     if (pow) { if (logda) PM_OOP(true, true, true); else PM_OOP(true, true, false); }
     else { if (logda) PM_OOP(true, false, true); else PM_OOP(true, false, false); }
