@@ -25,6 +25,7 @@ import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -48,10 +49,16 @@ def log(*a):
 
 
 def kernel_hash():
+    """sha256[:16] of the kernel sources' code: comments removed and runs of
+    whitespace collapsed, so that editing a comment does not orphan the
+    committed counter summary, while any change to the code does."""
     h = hashlib.sha256()
     for path in KERNEL_SRCS:
-        with open(path, "rb") as fh:
-            h.update(fh.read())
+        with open(path, encoding="utf-8") as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -19,9 +19,10 @@
 //
 // Each grid row stores its 9 + 5 population rows one after the other (x
 // fastest, rows padded to 64 elements), so a node update touches one
-// contiguous block per grid row; one workgroup of 256 threads covers a
-// 256-node row segment, so every load and store of a wave is a contiguous
-// 256 B (FP32) run; workgroups run in row-major tile order.  The
+// contiguous block per grid row; one workgroup covers a row segment of 64,
+// 128 or 256 nodes (chosen by the host from the grid size and dtype), one
+// lane per node, so every load and store of a wave is a contiguous 256 B
+// (FP32) run; workgroups run in row-major tile order.  The
 // streaming hint is used on every access that is not shifted along x (those
 // lines are touched exactly once per step); the x-shifted accesses of the odd
 // step straddle lines that the neighbouring wave also touches, so they keep
