@@ -39,9 +39,14 @@ STEPS_PER_LAUNCH = 2  # the FP32 cavity runs the two-step kernel
 HBM_PEAK_GBS = 8000.0
 CHECK_EVERY = 1000
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step2_fp32_4096_traffic.txt")
-# the step kernel's source: the kernel file and the per-node device code it includes
-KERNEL_SRCS = [os.path.join(ROOT, "paper_2011_15073_amd", "csrc", f)
-               for f in ("pm_kernels.hip", "pm_device.h", "pm_internal.h")]
+# the code that decides what the two-step kernel computes and moves: the
+# per-node device code and parameters (whole files), the kernel and its
+# launcher, and the host's choice of rows per workgroup
+CSRC = os.path.join(ROOT, "paper_2011_15073_amd", "csrc")
+KERNEL_SRCS = [os.path.join(CSRC, "pm_device.h"), os.path.join(CSRC, "pm_internal.h"),
+               (os.path.join(CSRC, "pm_kernels.hip"), r"// ---- two time steps in one pass.*?(?=// ---- )"),
+               (os.path.join(CSRC, "pm_kernels.hip"), r"hipError_t launch_step2\(.*?\n}\n"),
+               (os.path.join(CSRC, "pm_api.hip"), r"int pair_rows_for\(.*?\n}\n")]
 
 
 def log(*a):
@@ -49,13 +54,20 @@ def log(*a):
 
 
 def kernel_hash():
-    """sha256[:16] of the kernel sources' code: comments removed and runs of
-    whitespace collapsed, so that editing a comment does not orphan the
-    committed counter summary, while any change to the code does."""
+    """sha256[:16] of the two-step kernel's code (KERNEL_SRCS: whole files or
+    the part a pattern selects), comments removed and runs of whitespace
+    collapsed: editing a comment or another kernel keeps the committed
+    counter summary, any change to this kernel's code orphans it."""
     h = hashlib.sha256()
-    for path in KERNEL_SRCS:
+    for src in KERNEL_SRCS:
+        path, pattern = src if isinstance(src, tuple) else (src, None)
         with open(path, encoding="utf-8") as fh:
             text = fh.read()
+        if pattern is not None:
+            m = re.search(pattern, text, flags=re.S)
+            if m is None:
+                raise RuntimeError(f"kernel_hash: {pattern!r} not found in {path}")
+            text = m.group(0)
         text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
         text = re.sub(r"//[^\n]*", " ", text)
         h.update(" ".join(text.split()).encode())
@@ -255,6 +267,41 @@ def adjoint_main(args):
         "dJ_dn": gn, "dJ_dRa": gRa, "max_abs_dJ_dlogDa": float(gld.abs().max())}), flush=True)
 
 
+def psi_main(args):
+    """Stream function of the 4096^2 workload (FP32 state after the warm-up
+    steps, FP64 psi): one pm_stream_function call = the porous-velocity field
+    kernel (reads the 14 populations, writes U) and the three-pass blocked
+    column scan.  Algorithmic bytes per node: 56 (populations) + 8 (U) + 8
+    (U, block sums) + 16 (U read, psi written) = 88."""
+    import torch
+    import paper_2011_15073_amd as P
+
+    cav = P.Cavity(N, dtype="fp32", device="cuda:0", **PHYS)
+    cav.step(args.warmup)
+    psi = cav.stream_function()
+    torch.cuda.synchronize()
+    reps = 20
+    with torch.cuda.stream(cav.stream):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(cav.stream)
+        for _ in range(reps):
+            cav.stream_function(out=psi)
+        e1.record(cav.stream)
+    e1.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / reps
+    alg = 88 * N * N
+    log(f"psi: {us:.1f} us per call, {alg / us / 1e3:.0f} GB/s algorithmic")
+    print(json.dumps({
+        "metric": "stream function time", "value": round(us, 2), "unit": "us", "n_gpus": 1,
+        "higher_is_better": False, "dtype": "f32 state / f64 psi", "data": "synthetic",
+        "config": {"workload": f"stream function of the porous power-law cavity {N}x{N} after "
+                               f"{args.warmup} steps (n=0.8 Da=1e-2 Ra=1e5 Pr=10 eps=0.6)"},
+        "roofline": {"bound": "hbm", "achieved": round(alg / us / 1e3, 1), "peak": 8000.0, "unit": "GB/s",
+                     "frac": round(alg / us / 1e3 / 8000.0, 4), "traffic": None,
+                     "algorithmic_bytes_per_call": alg}}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -270,6 +317,8 @@ def main():
     ap.add_argument("--paper-tables", action="store_true",
                     help="run the paper's validation and parametric cases and print Nu beside its values")
     ap.add_argument("--paper-side", type=int, default=160)
+    ap.add_argument("--stream-function", action="store_true",
+                    help="time the stream function of the 4096^2 workload")
     ap.add_argument("--adjoint", action="store_true",
                     help="time the gradient of Nu (forward with checkpoints vs backward)")
     ap.add_argument("--adjoint-steps", type=int, default=5000)
@@ -288,6 +337,9 @@ def main():
         return paper_main(args)
     if args.adjoint:
         adjoint_main(args)
+        return
+    if args.stream_function:
+        psi_main(args)
         return
 
     import torch

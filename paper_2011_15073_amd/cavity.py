@@ -109,11 +109,16 @@ class Cavity:
         self._check(lib.pm_fields(self._h, *(C.c_void_p(t.data_ptr()) for t in out), code))
         return tuple(out)
 
-    def stream_function(self, dtype=torch.float64):
+    def stream_function(self, dtype=torch.float64, out=None):
         """Nondimensional stream function psi [ny, nx] (psi = 0 on the bottom
-        wall; U = d psi / dY, V = -d psi / dX)."""
-        code = _dt_code(dtype)
-        out = torch.empty((self.ny, self.nx), dtype=_TORCH_DT[code], device=self.device)
+        wall; U = d psi / dY, V = -d psi / dX), into ``out`` if given (a
+        contiguous [ny, nx] tensor of this device, float32 or float64)."""
+        if out is None:
+            code = _dt_code(dtype)
+            out = torch.empty((self.ny, self.nx), dtype=_TORCH_DT[code], device=self.device)
+        else:
+            code = _dt_code(out.dtype)
+            assert out.is_contiguous() and tuple(out.shape) == (self.ny, self.nx) and out.device == self.device
         self._check(lib.pm_stream_function(self._h, C.c_void_p(out.data_ptr()), code))
         return out
 

@@ -41,7 +41,7 @@ struct Layout {
   size_t qs, rs;     // population stride, row stride (elements), see pm::KParams
   size_t plane;      // pitch of the per-cell planes (log10 Da, snapshot), elements
   size_t pop_bytes;  // the population region (f and g, padding included)
-  size_t off_f, off_g, off_logda, off_snap, off_red, total;
+  size_t off_f, off_g, off_logda, off_snap, off_red, off_scan, total;
   size_t off_pair;   // second population region for the two-step kernel (0: none)
 };
 
@@ -126,6 +126,8 @@ Layout layout_of(const pm_params& p, bool pair = false) {
   o = align_up(o + L.plane * L.elem);
   L.off_red = o;
   o = align_up(o + (pm::RED_BLOCKS + 16) * sizeof(double));
+  L.off_scan = o;  // block sums of the stream-function scan
+  o = align_up(o + pm::stream_scratch_bytes(p.nx, p.ny));
   if (pair) {
     o = (o + (size_t(1) << 21) - 1) / (size_t(1) << 21) * (size_t(1) << 21);  // 2 MiB, like the base
     L.off_pair = o;
@@ -603,7 +605,8 @@ int pm_stream_function(pm_ctx* c, void* psi, int dtype) {
                              nullptr, nullptr, dtype == PM_FP64);
   });
   if (e == hipSuccess)
-    e = pm::launch_stream_y(psi, c->p.nx, c->p.ny, 1.0 / (double)c->p.nx, dtype == PM_FP64, c->stream);
+    e = pm::launch_stream_y(psi, c->p.nx, c->p.ny, 1.0 / (double)c->p.nx, dtype == PM_FP64,
+                            (double*)((char*)c->ws + c->lay.off_scan), c->stream);
   return check_hip(c, e, "pm_stream_function");
 }
 

@@ -157,7 +157,11 @@ hipError_t launch_write_header(void* dst, int64_t steps, uint64_t tag, hipStream
 // natural-layout state in src (even step count) to dst.
 hipError_t launch_step2(const KParams<float>& src, const KParams<float>& dst, hipStream_t s, bool pow,
                         bool logda, int rows);
-hipError_t launch_stream_y(void* psi, int nx, int ny, double inv_L, int out_fp64, hipStream_t s);
+// Stream function up each column, in place on the U field in psi; scratch:
+// stream_scratch_bytes(nx, ny) bytes of device memory.
+size_t stream_scratch_bytes(int nx, int ny);
+hipError_t launch_stream_y(void* psi, int nx, int ny, double inv_L, int out_fp64, double* scratch,
+                           hipStream_t s);
 hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, hipStream_t s);
 
 }  // namespace pm

@@ -409,18 +409,62 @@ __global__ void k_header(int64_t* dst, int64_t steps, uint64_t tag) {
   }
 }
 
-// Stream function from the U field, in place: on entry psi holds U
-// (nondimensional) at the nodes, on exit psi = (1/L) * integral of U dy from
-// the bottom wall (y = 0, psi = 0) to the node (y = j + 1/2): the cells below
-// the node contribute their full value, the node's own cell half.  One thread
-// per column walks up the rows, so each row access of a wave is contiguous;
-// the running sum is FP64.
+// Stream function from the U field, in place: on entry psi holds U at the
+// nodes, on exit psi(j) = (sum_{j' < j} U(j') + U(j) / 2) / L up each column
+// (the integral of U dy from the bottom wall to the node by the midpoint
+// rule), as a blocked scan with FP64 sums: (1) every thread sums one
+// column over one block of R rows; (2) one thread per column turns the
+// block sums into exclusive block offsets; (3) every (column, block) thread
+// walks its rows from its block's offset.  A wave reads 64 adjacent columns
+// of a row at a time, so every access is contiguous.
+// Rows per block: 64, doubled until the block count fits a launch's y extent.
+inline int psi_rows(int ny) {
+  int r = 64;
+  while ((ny + r - 1) / r > 65535) r *= 2;
+  return r;
+}
+
 template <typename O>
-__global__ __launch_bounds__(256) void k_stream_y(O* psi, int nx, int ny, double inv_L) {
+__global__ __launch_bounds__(256) void k_psi_blocks(const O* __restrict__ u, double* __restrict__ blk, int nx,
+                                                    int ny, int R) {
+  const int i = blockIdx.x * 256 + threadIdx.x, b = blockIdx.y;
+  if (i >= nx) return;
+  const int j1 = (int)min((int64_t)ny, (int64_t)(b + 1) * R);
+  double s = 0.0;
+#pragma unroll 8
+  for (int j = b * R; j < j1; ++j) s += (double)u[(int64_t)j * nx + i];
+  blk[(int64_t)b * nx + i] = s;
+}
+
+// Exclusive prefix over the block sums of each column, in order.  The sums
+// are loaded 16 at a time before any is overwritten, so the loads of a
+// group are in flight together.
+__global__ __launch_bounds__(256) void k_psi_offsets(double* __restrict__ blk, int nx, int nblk) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= nx) return;
+  constexpr int G = 16;
   double acc = 0.0;
-  for (int j = 0; j < ny; ++j) {
+  for (int b0 = 0; b0 < nblk; b0 += G) {
+    double s[G];
+#pragma unroll
+    for (int t = 0; t < G; ++t) s[t] = b0 + t < nblk ? blk[(int64_t)(b0 + t) * nx + i] : 0.0;
+#pragma unroll
+    for (int t = 0; t < G; ++t) {
+      if (b0 + t < nblk) blk[(int64_t)(b0 + t) * nx + i] = acc;
+      acc += s[t];
+    }
+  }
+}
+
+template <typename O>
+__global__ __launch_bounds__(256) void k_psi_apply(O* __restrict__ psi, const double* __restrict__ blk, int nx,
+                                                   int ny, int R, double inv_L) {
+  const int i = blockIdx.x * 256 + threadIdx.x, b = blockIdx.y;
+  if (i >= nx) return;
+  const int j1 = (int)min((int64_t)ny, (int64_t)(b + 1) * R);
+  double acc = blk[(int64_t)b * nx + i];
+#pragma unroll 8
+  for (int j = b * R; j < j1; ++j) {
     const int64_t k = (int64_t)j * nx + i;
     const double u = (double)psi[k];
     psi[k] = (O)((acc + 0.5 * u) * inv_L);
@@ -605,12 +649,26 @@ hipError_t launch_write_header(void* dst, int64_t steps, uint64_t tag, hipStream
   return hipGetLastError();
 }
 
-hipError_t launch_stream_y(void* psi, int nx, int ny, double inv_L, int out_fp64, hipStream_t s) {
-  const dim3 grid((unsigned)((nx + 255) / 256));
+size_t stream_scratch_bytes(int nx, int ny) {
+  const int R = psi_rows(ny);
+  return (size_t)nx * (size_t)((ny + R - 1) / R) * sizeof(double);
+}
+
+hipError_t launch_stream_y(void* psi, int nx, int ny, double inv_L, int out_fp64, double* scratch,
+                           hipStream_t s) {
+  const int R = psi_rows(ny), nblk = (ny + R - 1) / R;
+  const dim3 grid((unsigned)((nx + 255) / 256), (unsigned)nblk);
   if (out_fp64)
-    hipLaunchKernelGGL((k_stream_y<double>), grid, dim3(256), 0, s, (double*)psi, nx, ny, inv_L);
+    hipLaunchKernelGGL((k_psi_blocks<double>), grid, dim3(256), 0, s, (const double*)psi, scratch, nx, ny, R);
   else
-    hipLaunchKernelGGL((k_stream_y<float>), grid, dim3(256), 0, s, (float*)psi, nx, ny, inv_L);
+    hipLaunchKernelGGL((k_psi_blocks<float>), grid, dim3(256), 0, s, (const float*)psi, scratch, nx, ny, R);
+  hipLaunchKernelGGL(k_psi_offsets, dim3(grid.x), dim3(256), 0, s, scratch, nx, nblk);
+  if (out_fp64)
+    hipLaunchKernelGGL((k_psi_apply<double>), grid, dim3(256), 0, s, (double*)psi, (const double*)scratch, nx,
+                       ny, R, inv_L);
+  else
+    hipLaunchKernelGGL((k_psi_apply<float>), grid, dim3(256), 0, s, (float*)psi, (const double*)scratch, nx, ny,
+                       R, inv_L);
   return hipGetLastError();
 }
 

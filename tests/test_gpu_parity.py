@@ -282,6 +282,24 @@ def test_stream_function():
     assert np.abs(psi32 - psi).max() <= 1e-6 * scale
 
 
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+def test_stream_function_tall_grid(dtype):
+    """The column scan over several row blocks with a ragged last block (37 x
+    150 and 300 x 1030, from random states): psi against its definition applied
+    to the same cavity's U field, in FP64."""
+    for nx, ny in ((37, 150), (300, 1030)):
+        f0, g0 = inputs.random_state(nx, ny, seed=7, amp=0.05)
+        cav = gpu_for(nx, ny, dtype=dtype, **CFG0)
+        cav.set_populations(torch.from_numpy(f0), torch.from_numpy(g0))
+        cav.step(3)
+        U = cav.fields(torch.float64)[0].cpu().numpy()
+        psi = cav.stream_function().cpu().numpy()
+        ref = (np.cumsum(U, axis=0) - 0.5 * U) / nx
+        err = np.abs(psi - ref).max() / np.abs(ref).max()
+        log(f"psi {nx}x{ny} {dtype}: max|psi| {np.abs(ref).max():.3e}, rel err {err:.2e}")
+        assert err <= 1e-12
+
+
 PAIR_SIZES = [(8, 8), (33, 21), (252, 70), (300, 130), (520, 67)]
 
 
