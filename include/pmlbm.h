@@ -166,9 +166,10 @@ int pm_fields(pm_ctx* ctx, void* U, void* V, void* theta, int dtype);
  * the paper's results section): psi with U = d psi / dY, V = -d psi / dX in
  * the nondimensional units of pm_fields (Y = y / L, L = nx), psi = 0 on the
  * bottom wall, integrated up each column by the midpoint rule
- * (psi_j = (sum_{j' < j} U_j' + U_j / 2) / L) with an FP64 running sum.
- * Closed streamlines are level sets; psi on the top wall is the column's net
- * flux (0 for a steady incompressible flow).  Async. */
+ * (psi_j = (sum_{j' < j} U_j' + U_j / 2) / L) with FP64 sums (a blocked
+ * scan over 64-row blocks; scratch space is part of the workspace).  Closed
+ * streamlines are level sets; psi on the top wall is the column's net flux
+ * (0 for a steady incompressible flow).  Async. */
 int pm_stream_function(pm_ctx* ctx, void* psi, int dtype);
 
 /* Local lattice viscosity nu(x) of the current state [ny][nx].  Async. */
