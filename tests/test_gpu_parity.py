@@ -81,6 +81,35 @@ def test_random_state_steps_fp64(ci, logda, grid):
     assert rel_err(nu_g, orc.macros()["nu"]) <= 1e-12
 
 
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+def test_random_state_mid_size(dtype):
+    """A 600 x 500 grid from a random non-equilibrium state: above 512^2 the
+    single-step kernels run 128-node (FP64) and 256-node (FP32) row segments
+    per workgroup.  FP64 populations to 1e-13 after 1, 2 and 5 steps; FP32
+    fields to the 1e-4 bar."""
+    kw = RANDOM_CASES[1]
+    nx, ny = 600, 500
+    f0, g0 = inputs.random_state(nx, ny, seed=21, amp=0.05)
+    log("case: 600x500 random state", dtype, kw)
+    cav = gpu_for(nx, ny, dtype=dtype, **kw)
+    cav.set_populations(torch.from_numpy(f0), torch.from_numpy(g0))
+    orc = oracle_for(nx, ny, **kw)
+    orc.set_state(f0, g0)
+    for k in (1, 1, 3):
+        cav.step(k)
+        orc.step(k)
+        if dtype == "fp64":
+            fg, gg = (t.cpu().numpy() for t in cav.populations(torch.float64))
+            fr, gr = orc.state()
+            ef, eg = np.abs(fg - fr).max(), np.abs(gg - gr).max()
+            log("  after", orc.steps, "steps: pop err", ef, eg)
+            assert ef <= 1e-13 and eg <= 1e-13
+        else:
+            errs = compare_fields(cav, orc)
+            log("  after", orc.steps, "steps:", errs)
+            assert max(errs.values()) <= 1e-4
+
+
 SIZES = [(8, 8), (33, 33), (96, 96), (257, 40), (300, 37)]
 
 
