@@ -12,7 +12,6 @@ import math
 
 import torch
 
-from . import _lib
 from ._lib import check, lib
 from .cavity import Cavity
 

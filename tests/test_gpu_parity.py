@@ -14,7 +14,6 @@ import numpy as np
 import pytest
 import torch
 
-import oracle as O
 from paper_2011_15073_amd import inputs
 from pairs import compare_fields, compare_nu, gpu_for, gpu_fields, oracle_for, rel_err
 
