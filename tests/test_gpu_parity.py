@@ -109,6 +109,33 @@ def test_random_state_mid_size(dtype):
             assert max(errs.values()) <= 1e-4
 
 
+@pytest.mark.parametrize("grid", [(2, 2), (2, 5), (5, 2), (3, 3)])
+def test_smallest_grids(grid):
+    """Grids where every node touches a wall (the 2 x 2 minimum, one-node-wide
+    strips): FP64 populations against the oracle from a random state after 1,
+    2 and 5 steps, for a power-law and a Newtonian case; step(0) changes
+    nothing."""
+    nx, ny = grid
+    for ci in (0, 1):
+        kw = RANDOM_CASES[ci]
+        f0, g0 = inputs.random_state(nx, ny, seed=31 + ci, amp=0.05)
+        cav = gpu_for(nx, ny, dtype="fp64", **kw)
+        cav.set_populations(torch.from_numpy(f0), torch.from_numpy(g0))
+        cav.step(0)
+        assert cav.steps == 0
+        fz, gz = (t.cpu().numpy() for t in cav.populations(torch.float64))
+        assert np.abs(fz - f0).max() <= 1e-15 and np.abs(gz - g0).max() <= 1e-15
+        orc = oracle_for(nx, ny, **kw)
+        orc.set_state(f0, g0)
+        for k in (1, 1, 3):
+            cav.step(k)
+            orc.step(k)
+            fg, gg = (t.cpu().numpy() for t in cav.populations(torch.float64))
+            fr, gr = orc.state()
+            assert np.abs(fg - fr).max() <= 1e-13 and np.abs(gg - gr).max() <= 1e-13, (grid, ci, orc.steps)
+        assert abs(cav.nu() - orc.nu_bar()) <= 1e-12 * max(1.0, abs(orc.nu_bar()))
+
+
 SIZES = [(8, 8), (33, 33), (96, 96), (257, 40), (300, 37)]
 
 
