@@ -111,6 +111,26 @@ def test_tile_shape_does_not_change_results(dtype, tile):
         assert torch.equal(fa, fb) and torch.equal(ga, gb), i
 
 
+@pytest.mark.parametrize("tile", [(256, 1), (64, 4)])
+def test_sweep_with_smallest_grids(tile):
+    """2 x 2 and 5 x 2 cavities (every node on a wall) beside a ragged 300 x 7
+    one: every case bitwise equal to the case run alone, for 1 and 4 rows per
+    tile."""
+    cases = [dict(nx=2, ny=2, n=0.6, Da=1e-2, Ra=1e4, Pr=10.0, eps=0.6, dtype="fp64"),
+             dict(nx=5, ny=2, n=1.0, Da=1e-1, Ra=1e3, Pr=10.0, eps=0.6, dtype="fp64"),
+             dict(nx=300, ny=7, n=0.8, Da=1e-3, Ra=1e5, Pr=10.0, eps=0.6, dtype="fp64")]
+    sw = P.Sweep(cases, tile=tile)
+    sw.step(37)
+    for i, kw in enumerate(cases):
+        kw = dict(kw)
+        nx, ny = kw.pop("nx"), kw.pop("ny")
+        alone = P.Cavity(nx, ny, **kw)
+        alone.step(37)
+        fa, ga = alone.populations(torch.float64)
+        fb, gb = sw.case(i).populations(torch.float64)
+        assert torch.equal(fa, fb) and torch.equal(ga, gb), i
+
+
 def test_unsupported_tile_shape_is_rejected():
     sw = P.Sweep([dict(CASES[0], dtype="fp32")])
     for bad in ((32, 1), (256, 2), (96, 1), (64, 3)):
