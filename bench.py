@@ -35,31 +35,43 @@ sys.path.insert(0, ROOT)
 N = 4096
 PHYS = dict(n=0.8, Da=1e-2, Ra=1e5, Pr=10.0, eps=0.6)
 BYTES_PER_NODE = 112  # 14 FP32 populations, each read once and written once per step
-STEPS_PER_LAUNCH = 2  # the FP32 cavity runs the two-step kernel
 HBM_PEAK_GBS = 8000.0
 CHECK_EVERY = 1000
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step2_fp32_4096_traffic.txt")
-# the code that decides what the two-step kernel computes and moves: the
-# per-node device code and parameters (whole files), the kernel and its
-# launcher, and the host's choice of rows per workgroup
 CSRC = os.path.join(ROOT, "paper_2011_15073_amd", "csrc")
-KERNEL_SRCS = [os.path.join(CSRC, "pm_device.h"), os.path.join(CSRC, "pm_internal.h"),
-               (os.path.join(CSRC, "pm_kernels.hip"), r"// ---- two time steps in one pass.*?(?=// ---- )"),
-               (os.path.join(CSRC, "pm_kernels.hip"), r"hipError_t launch_step2\(.*?\n}\n"),
-               (os.path.join(CSRC, "pm_api.hip"), r"int pair_rows_for\(.*?\n}\n")]
+# The step kernels the benchmark can time (--step-kernel; the default "auto"
+# takes the two-step kernel at 4096^2), each with its committed counter
+# summary and the code that decides what it computes and moves: the per-node
+# device code and parameters (whole files), the kernel and its launcher, and
+# the host's launch-shape choice.
+KERNELS = {
+    "pair": dict(
+        name="k_step2 (two fused stream+collide steps per launch, LDS row rings)", steps_per_launch=2,
+        traffic_file=os.path.join(ROOT, "profiles", "k_step2_fp32_4096_traffic.txt"),
+        srcs=[os.path.join(CSRC, "pm_device.h"), os.path.join(CSRC, "pm_internal.h"),
+              (os.path.join(CSRC, "pm_kernels.hip"), r"// ---- two time steps in one pass.*?(?=// ---- )"),
+              (os.path.join(CSRC, "pm_kernels.hip"), r"hipError_t launch_step2\(.*?\n}\n"),
+              (os.path.join(CSRC, "pm_api.hip"), r"int pair_rows_for\(.*?\n}\n")]),
+    "single": dict(
+        name="k_step (one fused stream+collide step per launch, AA pattern in place)", steps_per_launch=1,
+        traffic_file=os.path.join(ROOT, "profiles", "k_step_fp32_4096_traffic.txt"),
+        srcs=[os.path.join(CSRC, "pm_device.h"), os.path.join(CSRC, "pm_internal.h"),
+              (os.path.join(CSRC, "pm_kernels.hip"), r"void k_step\(KParams<T> p.*?\n}\n"),
+              (os.path.join(CSRC, "pm_kernels.hip"), r"hipError_t launch_step\(.*?\n}\n"),
+              (os.path.join(CSRC, "pm_api.hip"), r"int step_width_for\(.*?\n}\n")]),
+}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_hash():
-    """sha256[:16] of the two-step kernel's code (KERNEL_SRCS: whole files or
-    the part a pattern selects), comments removed and runs of whitespace
-    collapsed: editing a comment or another kernel keeps the committed
-    counter summary, any change to this kernel's code orphans it."""
+def kernel_hash(kind="pair"):
+    """sha256[:16] of a step kernel's code (KERNELS[kind]["srcs"]: whole
+    files or the part a pattern selects), comments removed and runs of
+    whitespace collapsed: editing a comment or another kernel keeps the
+    committed counter summary, any change to this kernel's code orphans it."""
     h = hashlib.sha256()
-    for src in KERNEL_SRCS:
+    for src in KERNELS[kind]["srcs"]:
         path, pattern = src if isinstance(src, tuple) else (src, None)
         with open(path, encoding="utf-8") as fh:
             text = fh.read()
@@ -74,18 +86,19 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def read_traffic():
-    """HBM bytes per step launch from the committed rocprofv3 counter summary
-    (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or None
-    when absent or taken on a different kernel source."""
-    if not os.path.exists(TRAFFIC_FILE):
+def read_traffic(kind="pair"):
+    """HBM bytes per launch of a step kernel from its committed rocprofv3
+    counter summary (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel
+    calibration), or None when absent or taken on different kernel code."""
+    path = KERNELS[kind]["traffic_file"]
+    if not os.path.exists(path):
         return None
     vals = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if "=" in line and not line.lstrip().startswith("#"):
             k, v = line.split("=", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_sha256_16") != kernel_hash():
+    if vals.get("kernel_source_sha256_16") != kernel_hash(kind):
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
@@ -308,6 +321,8 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--step-kernel", default="auto", choices=["auto", "single", "pair"],
+                    help="step kernel of the cavity (auto: the two-step kernel at 4096^2)")
     ap.add_argument("--roofline-steps", type=int, default=400)
     ap.add_argument("--sweep", action="store_true",
                     help="run the 27-case batched-sweep benchmark instead")
@@ -347,8 +362,11 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    log(f"bench: {N}x{N} fp32 {PHYS}, warmup {args.warmup}, steps {args.steps}")
-    cav = P.Cavity(N, dtype="fp32", device="cuda:0", **PHYS)
+    kind = "single" if args.step_kernel == "single" else "pair"  # "auto" takes the pair kernel at 4096^2
+    K = KERNELS[kind]
+    spl = K["steps_per_launch"]
+    log(f"bench: {N}x{N} fp32 {PHYS}, warmup {args.warmup}, steps {args.steps}, step kernel {args.step_kernel}")
+    cav = P.Cavity(N, dtype="fp32", device="cuda:0", step_kernel=args.step_kernel, **PHYS)
     stream = cav.stream
 
     # warm-up (also builds the step graphs)
@@ -375,9 +393,9 @@ def main():
     mlups = N * N * args.steps / elapsed / 1e6
     log(f"bench: {mlups:.1f} MLUPS, {ms_per_step:.4f} ms/step, Nu {nus[-1] if nus else cav.nu():.6f}")
 
-    # roofline of the two-step kernel: back-to-back launches (rs steps from an
-    # even step count: rs / 2 launches) bracketed by HIP events on the
-    # context's stream
+    # roofline of the step kernel: back-to-back launches (for the two-step
+    # kernel rs steps from an even step count: rs / 2 launches) bracketed by
+    # HIP events on the context's stream
     rs = args.roofline_steps - args.roofline_steps % 4
     with torch.cuda.stream(stream):
         e0 = torch.cuda.Event(enable_timing=True)
@@ -387,9 +405,9 @@ def main():
         e1.record(stream)
     e1.synchronize()
     per_step_s = e0.elapsed_time(e1) / 1e3 / rs
-    launch_s = STEPS_PER_LAUNCH * per_step_s
-    achieved = BYTES_PER_NODE * N * N * STEPS_PER_LAUNCH / launch_s / 1e9
-    log(f"bench: two-step kernel {launch_s * 1e6:.1f} us/launch ({per_step_s * 1e6:.1f} us/step), "
+    launch_s = spl * per_step_s
+    achieved = BYTES_PER_NODE * N * N * spl / launch_s / 1e9
+    log(f"bench: {K['name'].split()[0]} {launch_s * 1e6:.1f} us/launch ({per_step_s * 1e6:.1f} us/step), "
         f"{achieved:.0f} GB/s algorithmic")
 
     # measured streaming-copy ceiling (read + write of 1 GiB)
@@ -410,7 +428,7 @@ def main():
     del src, dst
     log(f"bench: copy ceiling {copy_gbs:.0f} GB/s")
 
-    traffic = read_traffic()
+    traffic = read_traffic(kind)
     result = {
         "metric": "MLUPS (flow+thermal)",
         "value": round(mlups, 1),
@@ -427,14 +445,14 @@ def main():
         "config": {"workload": "porous power-law cavity 4096x4096, D2Q9 MRT + D2Q5 MRT, "
                                "FP32 AA layout, n=0.8 Da=1e-2 Ra=1e5 Pr=10 eps=0.6, "
                                "Nu + residual on device every 1000 steps",
-                   "nodes": N * N, "steps_timed": args.steps},
+                   "nodes": N * N, "steps_timed": args.steps, "step_kernel": args.step_kernel},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
-                     "kernel": "k_step2 (two fused stream+collide steps per launch, LDS row rings)",
-                     "steps_per_launch": STEPS_PER_LAUNCH,
+                     "kernel": K["name"],
+                     "steps_per_launch": spl,
                      "us_per_launch": round(launch_s * 1e6, 2),
-                     "algorithmic_bytes_per_launch": BYTES_PER_NODE * N * N * STEPS_PER_LAUNCH,
+                     "algorithmic_bytes_per_launch": BYTES_PER_NODE * N * N * spl,
                      "copy_ceiling_GBps": round(copy_gbs, 1)},
         "nu_bar": nus[-1] if nus else None,
     }
