@@ -64,13 +64,14 @@ def nu_after(N, T, ld, n, Ra, dtype="fp64"):
     return c.nu()
 
 
-def test_adjoint_trajectory_matches_autograd():
+@pytest.mark.parametrize("N,T,C", [(12, 40, 7), (16, 50, None)])
+def test_adjoint_trajectory_matches_autograd(N, T, C):
     """Full trajectory (checkpointed, replayed segments) vs autograd through
-    the torch re-implementation: 12 x 12 cavity, 40 steps."""
-    N, T, n, Ra = 12, 40, 0.7, 1e4
+    the torch re-implementation (FP64 state): every gradient to 1e-9."""
+    n, Ra = 0.7, 1e4
     ld = inputs.logda_field(N, seed=5)
     cav = P.Cavity(N, dtype="fp64", logda=torch.from_numpy(ld), n=n, Ra=Ra, **PHYS)
-    adj = P.Adjoint(cav, T, 7)
+    adj = P.Adjoint(cav, T, C) if C else P.Adjoint(cav, T)
     J = adj.forward()
     gld, gn, gRa = adj.backward()
     nt = torch.tensor(n, dtype=torch.float64, requires_grad=True)
@@ -82,10 +83,12 @@ def test_adjoint_trajectory_matches_autograd():
         f, g = TS.step(Pm, f, g, ldt)
     Jt = TS.nu_bar(Pm, g)
     Jt.backward()
+    e_ld = np.abs(gld.cpu().numpy() - ldt.grad.numpy()).max() / np.abs(ldt.grad.numpy()).max()
+    e_n = abs(gn - nt.grad.item()) / abs(nt.grad.item())
+    e_Ra = abs(gRa - Rat.grad.item()) / abs(Rat.grad.item())
+    print(f"{N}x{N}, {T} steps: J {J:.12f}, rel errors log-Da {e_ld:.2e}, n {e_n:.2e}, Ra {e_Ra:.2e}", flush=True)
     assert J == pytest.approx(Jt.item(), rel=1e-12)
-    assert np.abs(gld.cpu().numpy() - ldt.grad.numpy()).max() <= 1e-9 * np.abs(ldt.grad.numpy()).max()
-    assert gn == pytest.approx(nt.grad.item(), rel=1e-8)
-    assert gRa == pytest.approx(Rat.grad.item(), rel=1e-8)
+    assert e_ld <= 1e-9 and e_n <= 1e-9 and e_Ra <= 1e-9
 
 
 def test_adjoint_matches_finite_differences_fp64():
