@@ -323,6 +323,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--step-kernel", default="auto", choices=["auto", "single", "pair"],
                     help="step kernel of the cavity (auto: the two-step kernel at 4096^2)")
+    ap.add_argument("--rounding", default="nearest", choices=["nearest", "stochastic"],
+                    help="rounding of the FP32 population updates (PM_ROUND_*)")
     ap.add_argument("--roofline-steps", type=int, default=400)
     ap.add_argument("--sweep", action="store_true",
                     help="run the 27-case batched-sweep benchmark instead")
@@ -365,8 +367,10 @@ def main():
     kind = "single" if args.step_kernel == "single" else "pair"  # "auto" takes the pair kernel at 4096^2
     K = KERNELS[kind]
     spl = K["steps_per_launch"]
-    log(f"bench: {N}x{N} fp32 {PHYS}, warmup {args.warmup}, steps {args.steps}, step kernel {args.step_kernel}")
-    cav = P.Cavity(N, dtype="fp32", device="cuda:0", step_kernel=args.step_kernel, **PHYS)
+    log(f"bench: {N}x{N} fp32 {PHYS}, warmup {args.warmup}, steps {args.steps}, step kernel {args.step_kernel}, "
+        f"rounding {args.rounding}")
+    cav = P.Cavity(N, dtype="fp32", device="cuda:0", step_kernel=args.step_kernel, rounding=args.rounding,
+                   **PHYS)
     stream = cav.stream
 
     # warm-up (also builds the step graphs)
@@ -428,7 +432,7 @@ def main():
     del src, dst
     log(f"bench: copy ceiling {copy_gbs:.0f} GB/s")
 
-    traffic = read_traffic(kind)
+    traffic = read_traffic(kind) if args.rounding == "nearest" else None  # counters taken with nearest rounding
     result = {
         "metric": "MLUPS (flow+thermal)",
         "value": round(mlups, 1),
@@ -445,7 +449,8 @@ def main():
         "config": {"workload": "porous power-law cavity 4096x4096, D2Q9 MRT + D2Q5 MRT, "
                                "FP32 AA layout, n=0.8 Da=1e-2 Ra=1e5 Pr=10 eps=0.6, "
                                "Nu + residual on device every 1000 steps",
-                   "nodes": N * N, "steps_timed": args.steps, "step_kernel": args.step_kernel},
+                   "nodes": N * N, "steps_timed": args.steps, "step_kernel": args.step_kernel,
+                   "rounding": args.rounding},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,

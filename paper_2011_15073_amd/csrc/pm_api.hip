@@ -165,6 +165,10 @@ int map_params(const pm_params& p, pm_lattice& L, char* msg, size_t msglen) {
     return fail("step_kernel must be PM_STEP_AUTO, PM_STEP_SINGLE or PM_STEP_PAIR");
   if (p.step_kernel == PM_STEP_PAIR && (!PM_PAIR_STEP || p.dtype != PM_FP32 || p.periodic_x || p.periodic_y))
     return fail("PM_STEP_PAIR needs FP32 and cavity walls on both axes");
+  if (p.rounding != PM_ROUND_NEAREST && p.rounding != PM_ROUND_STOCHASTIC)
+    return fail("rounding must be PM_ROUND_NEAREST or PM_ROUND_STOCHASTIC");
+  if (p.rounding == PM_ROUND_STOCHASTIC && p.dtype != PM_FP32)
+    return fail("PM_ROUND_STOCHASTIC applies to FP32 storage only");
   const double N = (double)p.nx;
   memset(&L, 0, sizeof L);
   L.U_lb = p.mach / std::sqrt(3.0);
@@ -230,6 +234,7 @@ pm::KParams<T> kparams(const pm_params& p, const pm_lattice& L, void* ws, const 
   k.inv_n = (T)(1.0 / p.n);
   k.tol = sizeof(T) == 8 ? (T)1e-13 : (T)8e-6;
   k.max_it = sizeof(T) == 8 ? 40 : 12;
+  k.sr = (sizeof(T) == 4 && p.rounding == PM_ROUND_STOCHASTIC) ? 1 : 0;
   k.eps = (T)L.eps;
   k.inv_eps = (T)(1.0 / L.eps);
   k.invK = std::isinf(L.K) ? (T)0 : (T)(1.0 / L.K);

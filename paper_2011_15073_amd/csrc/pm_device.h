@@ -402,7 +402,36 @@ __device__ __forceinline__ void node_macros(const KParams<T>& p, int k, const T 
 }
 
 // The full local update: Steps 2-9 on shifted populations, in place.
-template <typename T, bool POW, bool LOGDA>
+// ---- stochastic rounding of the FP32 population updates (PM_ROUND_STOCHASTIC) ----
+// With round-to-nearest, a state near a steady flow rounds the same way step
+// after step, and the slowly decaying modes of the cavity accumulate that
+// fixed rounding pattern into a bias far above one rounding.  The update is
+// therefore written as f* = f + df (df from the moment changes) and added with
+// a dither xi uniform in (-1/2, 1/2) ulp of the sum: rounding a + (b + xi) to
+// nearest rounds a + b up or down with probability given by its position
+// between the two neighbours (stochastic rounding, to within 1/512 ulp with
+// 8-bit uniforms).  The uniforms come from a 32-bit integer mixer
+// (xorshift-multiply rounds) of the node index and of the node's incoming
+// populations, so the result is deterministic and the same in every kernel
+// that updates the node.
+__device__ __forceinline__ unsigned mix32(unsigned x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+
+// a + b rounded with the dither byte ub (0..255) of a uniform.
+__device__ __forceinline__ float dither_add(float a, float b, unsigned ub) {
+  const float s0 = a + b;
+  const float ulp = __uint_as_float(__float_as_uint(s0) & 0x7f800000u) * 0x1p-23f;  // 0 for 0 / subnormal
+  const float xi = (float)ub * (1.0f / 256.0f) + (0.5f / 256.0f - 0.5f);
+  return a + __builtin_fmaf(xi, ulp, b);
+}
+
+template <typename T, bool POW, bool LOGDA, bool SR = false>
 __device__ __forceinline__ void collide(const KParams<T>& p, int k, T df[9], T dg[5]) {
   T drho, rho, jx, jy, dT, Gx, Gy, nu, ux, uy, invK, invsK, m1, m7, m8;
   node_macros<T, POW, LOGDA>(p, k, df, dg, drho, rho, jx, jy, dT, Gx, Gy, nu, ux, uy, invK,
@@ -444,15 +473,42 @@ __device__ __forceinline__ void collide(const KParams<T>& p, int k, T df[9], T d
   const T b58 = (a0 + T(2) * a1) + a2;
   const T x1 = a3 - T(2) * a4, y1 = a5 - T(2) * a6;
   const T x5 = a3 + a4, y5 = a5 + a6;
-  df[0] = (a0 - T(4) * a1) + T(4) * a2;
-  df[1] = (b14 + x1) + a7;
-  df[2] = (b14 + y1) - a7;
-  df[3] = (b14 - x1) + a7;
-  df[4] = (b14 - y1) - a7;
-  df[5] = (b58 + x5) + (y5 + a8);
-  df[6] = (b58 - x5) + (y5 - a8);
-  df[7] = (b58 - x5) - (y5 - a8);
-  df[8] = (b58 + x5) - (y5 + a8);
+  unsigned h[4] = {0u, 0u, 0u, 0u};  // 16 dither bytes (SR)
+  if constexpr (SR) {
+    static_assert(sizeof(T) == 4, "stochastic rounding is for FP32 storage");
+    const unsigned seed = mix32((unsigned)k * 0x9e3779b1u ^ __float_as_uint(df[0]) ^
+                                __float_as_uint(dg[0]) * 0x85ebca77u ^ __float_as_uint(df[5]) * 0xc2b2ae3du);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) h[r] = mix32(seed + 0x632be5abu * (unsigned)(r + 1));
+    // the same back-transform applied to the moment changes ms - m (the
+    // density is conserved), added to the incoming populations
+    const T d1 = (ms1 - m1) * T(1.0 / 36.0), d2 = (ms2 - m2) * T(1.0 / 36.0);
+    const T d3 = (ms3 - jx) * T(1.0 / 6.0), d4 = (ms4 - m4) * T(1.0 / 12.0);
+    const T d5 = (ms5 - jy) * T(1.0 / 6.0), d6 = (ms6 - m6) * T(1.0 / 12.0);
+    const T d7 = (ms7 - m7) * T(0.25), d8 = (ms8 - m8) * T(0.25);
+    const T e14 = -d1 - T(2) * d2, e58 = T(2) * d1 + d2;
+    const T u1 = d3 - T(2) * d4, v1 = d5 - T(2) * d6;
+    const T u5 = d3 + d4, v5 = d5 + d6;
+    df[0] = dither_add(df[0], T(4) * (d2 - d1), h[0] & 0xffu);
+    df[1] = dither_add(df[1], (e14 + u1) + d7, (h[0] >> 8) & 0xffu);
+    df[2] = dither_add(df[2], (e14 + v1) - d7, (h[0] >> 16) & 0xffu);
+    df[3] = dither_add(df[3], (e14 - u1) + d7, h[0] >> 24);
+    df[4] = dither_add(df[4], (e14 - v1) - d7, h[1] & 0xffu);
+    df[5] = dither_add(df[5], (e58 + u5) + (v5 + d8), (h[1] >> 8) & 0xffu);
+    df[6] = dither_add(df[6], (e58 - u5) + (v5 - d8), (h[1] >> 16) & 0xffu);
+    df[7] = dither_add(df[7], (e58 - u5) - (v5 - d8), h[1] >> 24);
+    df[8] = dither_add(df[8], (e58 + u5) - (v5 + d8), h[2] & 0xffu);
+  } else {
+    df[0] = (a0 - T(4) * a1) + T(4) * a2;
+    df[1] = (b14 + x1) + a7;
+    df[2] = (b14 + y1) - a7;
+    df[3] = (b14 - x1) + a7;
+    df[4] = (b14 - y1) - a7;
+    df[5] = (b58 + x5) + (y5 + a8);
+    df[6] = (b58 - x5) + (y5 - a8);
+    df[7] = (b58 - x5) - (y5 - a8);
+    df[8] = (b58 + x5) - (y5 + a8);
+  }
   // Step 9: D2Q5 MRT thermal collision (flux moments relax to u T)
   const T Tabs = p.T_ref + dT;
   const T n1 = dg[1] - dg[3], n2 = dg[2] - dg[4];
@@ -462,21 +518,31 @@ __device__ __forceinline__ void collide(const KParams<T>& p, int k, T df[9], T d
   const T ns2 = n2 - p.s_g * (n2 - uy * Tabs);
   const T ns3 = n3 - p.sT_e * (n3 + T(2.0 / 3.0) * dT);
   const T ns4 = n4 - p.sT_nu * n4;
-  const T c0 = dT * T(0.2), c1 = ns1 * T(0.5), c2 = ns2 * T(0.5);
-  const T c3 = ns3 * T(0.05), c4 = ns4 * T(0.25);
-  const T c03 = c0 + c3;
-  dg[0] = c0 - T(4) * c3;
-  dg[1] = (c03 + c1) + c4;
-  dg[2] = (c03 + c2) - c4;
-  dg[3] = (c03 - c1) + c4;
-  dg[4] = (c03 - c2) - c4;
+  if constexpr (SR) {
+    const T e1 = (ns1 - n1) * T(0.5), e2 = (ns2 - n2) * T(0.5);
+    const T e3 = (ns3 - n3) * T(0.05), e4 = (ns4 - n4) * T(0.25);  // T is conserved
+    dg[0] = dither_add(dg[0], T(-4) * e3, (h[2] >> 8) & 0xffu);
+    dg[1] = dither_add(dg[1], (e3 + e1) + e4, (h[2] >> 16) & 0xffu);
+    dg[2] = dither_add(dg[2], (e3 + e2) - e4, h[2] >> 24);
+    dg[3] = dither_add(dg[3], (e3 - e1) + e4, h[3] & 0xffu);
+    dg[4] = dither_add(dg[4], (e3 - e2) - e4, (h[3] >> 8) & 0xffu);
+  } else {
+    const T c0 = dT * T(0.2), c1 = ns1 * T(0.5), c2 = ns2 * T(0.5);
+    const T c3 = ns3 * T(0.05), c4 = ns4 * T(0.25);
+    const T c03 = c0 + c3;
+    dg[0] = c0 - T(4) * c3;
+    dg[1] = (c03 + c1) + c4;
+    dg[2] = (c03 + c2) - c4;
+    dg[3] = (c03 - c1) + c4;
+    dg[4] = (c03 - c2) - c4;
+  }
 }
 
 // One row tile [i0, i0 + TILE) of row j: gather from the state p, collide,
 // scatter into the state d (d == p: the in-place AA update; d != p: the same
 // update written to another buffer, which then holds the complete next
 // state because every slot is written exactly once per step).
-template <typename T, bool ODD, bool POW, bool LOGDA>
+template <typename T, bool ODD, bool POW, bool LOGDA, bool SR = false>
 __device__ __forceinline__ void step_tile(const KParams<T>& p, const KParams<T>& d, int i0, int j, int lx) {
   const int i = i0 + lx;
   T df[9], dg[5];
@@ -488,14 +554,14 @@ __device__ __forceinline__ void step_tile(const KParams<T>& p, const KParams<T>&
     const bool interior = w0 >= 1 && w0 + 63 <= p.nx - 2 && j >= 1 && j <= p.ny - 2;
     if (interior) {
       load_interior_odd<T>(p, row_base(p, j), i, df, dg);
-      collide<T, POW, LOGDA>(p, j * p.nx + i, df, dg);
+      collide<T, POW, LOGDA, SR>(p, j * p.nx + i, df, dg);
       store_interior_odd<T>(d, row_base(d, j), i, df, dg);
       return;
     }
   }
   if (i >= p.nx) return;
   load_node<T, ODD>(p, i, j, df, dg);
-  collide<T, POW, LOGDA>(p, j * p.nx + i, df, dg);
+  collide<T, POW, LOGDA, SR>(p, j * p.nx + i, df, dg);
   store_node<T, ODD>(d, i, j, df, dg);
 }
 

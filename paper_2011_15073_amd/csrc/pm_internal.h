@@ -34,6 +34,7 @@ struct KParams {
   T nm1, inv_n;    // n - 1, 1 / n
   T tol;           // Newton tolerance on log2(nu)
   int max_it;
+  int sr;          // 1: round the FP32 population updates stochastically (PM_ROUND_STOCHASTIC)
   // porous medium
   T eps, inv_eps, invK, invsK, Feps, inv_Kscale;
   // body forces: G = (gx, gy + gbeta (T - T_m))

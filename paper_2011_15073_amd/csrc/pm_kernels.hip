@@ -29,25 +29,27 @@
 // the default caching.
 #include "pm_device.h"
 
+#include <type_traits>
+
 namespace pm {
 namespace {
 
 using namespace pm::dev;
 
 // One workgroup per row segment of blockDim.x nodes (64, 128 or 256).
-template <typename T, bool ODD, bool POW, bool LOGDA>
+template <typename T, bool ODD, bool POW, bool LOGDA, bool SR>
 __global__ __launch_bounds__(TILE) void k_step(KParams<T> p, int tiles_x, int ntiles) {
   const int tile = tile_of_block(blockIdx.x, ntiles);
   const int j = tile / tiles_x;
-  step_tile<T, ODD, POW, LOGDA>(p, p, (tile - j * tiles_x) * (int)blockDim.x, j, threadIdx.x);
+  step_tile<T, ODD, POW, LOGDA, SR>(p, p, (tile - j * tiles_x) * (int)blockDim.x, j, threadIdx.x);
 }
 
 // The same step, read from state src and written to state dst (another
 // buffer of the same layout).
-template <typename T, bool ODD, bool POW, bool LOGDA>
+template <typename T, bool ODD, bool POW, bool LOGDA, bool SR>
 __global__ __launch_bounds__(TILE) void k_step_oop(KParams<T> src, KParams<T> dst, int tiles_x) {
   const int j = blockIdx.x / tiles_x;
-  step_tile<T, ODD, POW, LOGDA>(src, dst, (blockIdx.x - j * tiles_x) * (int)blockDim.x, j, threadIdx.x);
+  step_tile<T, ODD, POW, LOGDA, SR>(src, dst, (blockIdx.x - j * tiles_x) * (int)blockDim.x, j, threadIdx.x);
 }
 
 // ---- two time steps in one pass (FP32, cavity walls) ----
@@ -111,7 +113,7 @@ __device__ __forceinline__ void pull_pair(const KParams<float>& p, float (*ring)
   dg[4] = yt ? hi.g4 : mid.g2;
 }
 
-template <bool POW, bool LOGDA>
+template <bool POW, bool LOGDA, bool SR>
 __global__ __launch_bounds__(TILE) void k_step2(KParams<float> src, KParams<float> dst, int rows) {
   __shared__ float ring1[3][NXS][TILE];  // f* of rows a - 2 .. a
   __shared__ float ring2[3][NXS][TILE];  // f** of rows a - 3 .. a - 1
@@ -131,7 +133,7 @@ __global__ __launch_bounds__(TILE) void k_step2(KParams<float> src, KParams<floa
       Still st{};
       if (col && a >= 0 && a < src.ny) {
         load_node<float, false>(src, c, a, df, dg);
-        collide<float, POW, LOGDA>(src, a * src.nx + c, df, dg);
+        collide<float, POW, LOGDA, SR>(src, a * src.nx + c, df, dg);
         put_row(ring1, s1, t, df, dg, st);
       }
       r1m = r10;
@@ -146,7 +148,7 @@ __global__ __launch_bounds__(TILE) void k_step2(KParams<float> src, KParams<floa
       if (b >= y0 - 1 && b >= 0 && b < src.ny && col && t >= 1 && t <= TILE - 2) {
         float df[9], dg[5];
         pull_pair(src, ring1, s1mm, s1m, s1, t, c, b, r1m, r10, r1p, df, dg);
-        collide<float, POW, LOGDA>(src, b * src.nx + c, df, dg);
+        collide<float, POW, LOGDA, SR>(src, b * src.nx + c, df, dg);
         put_row(ring2, s1m, t, df, dg, st);  // ring2 keeps row r in the slot ring1 gives row r
       }
       r2m = r20;
@@ -187,6 +189,13 @@ __global__ __launch_bounds__(TILE) void k_step_multi(const SweepCase<T>* __restr
   const int lx = (int)threadIdx.x % tw, j = ty * th + (int)threadIdx.x / tw;
   if (j >= c.p.ny) return;  // whole waves
   const int i0 = (e.y - ty * c.tiles_x) * tw;
+  if constexpr (std::is_same<T, float>::value) {
+    if (c.p.sr) {
+      if (c.pow) step_tile<T, ODD, true, false, true>(c.p, c.p, i0, j, lx);
+      else step_tile<T, ODD, false, false, true>(c.p, c.p, i0, j, lx);
+      return;
+    }
+  }
   if (c.pow) step_tile<T, ODD, true, false>(c.p, c.p, i0, j, lx);
   else step_tile<T, ODD, false, false>(c.p, c.p, i0, j, lx);
 }
@@ -494,15 +503,25 @@ template <typename T>
 hipError_t launch_step(const KParams<T>& p, const Launch& L, int parity, bool pow, bool logda) {
   if (!(L.step_w == 64 || L.step_w == 128 || L.step_w == 256) || L.step_w > TILE) return hipErrorInvalidValue;
   dim3 grid(L.step_ntiles), block(L.step_w);
-#define PM_STEP(ODD, POW, LOG) \
-  hipLaunchKernelGGL((k_step<T, ODD, POW, LOG>), grid, block, 0, L.stream, p, L.step_tiles_x, L.step_ntiles)
-  if (parity) {
-    if (pow) { if (logda) PM_STEP(true, true, true); else PM_STEP(true, true, false); }
-    else { if (logda) PM_STEP(true, false, true); else PM_STEP(true, false, false); }
-  } else {
-    if (pow) { if (logda) PM_STEP(false, true, true); else PM_STEP(false, true, false); }
-    else { if (logda) PM_STEP(false, false, true); else PM_STEP(false, false, false); }
+#define PM_STEP(ODD, POW, LOG, SR) \
+  hipLaunchKernelGGL((k_step<T, ODD, POW, LOG, SR>), grid, block, 0, L.stream, p, L.step_tiles_x, L.step_ntiles)
+#define PM_STEP_ALL(SR)                                                                             \
+  if (parity) {                                                                                     \
+    if (pow) { if (logda) PM_STEP(true, true, true, SR); else PM_STEP(true, true, false, SR); }       \
+    else { if (logda) PM_STEP(true, false, true, SR); else PM_STEP(true, false, false, SR); }        \
+  } else {                                                                                          \
+    if (pow) { if (logda) PM_STEP(false, true, true, SR); else PM_STEP(false, true, false, SR); }    \
+    else { if (logda) PM_STEP(false, false, true, SR); else PM_STEP(false, false, false, SR); }     \
   }
+  bool done = false;
+  if constexpr (std::is_same<T, float>::value) {
+    if (p.sr) {
+      PM_STEP_ALL(true)
+      done = true;
+    }
+  }
+  if (!done) { PM_STEP_ALL(false) }
+#undef PM_STEP_ALL
 #undef PM_STEP
   return hipGetLastError();
 }
@@ -511,13 +530,15 @@ hipError_t launch_step2(const KParams<float>& src, const KParams<float>& dst, hi
                         bool logda, int rows) {
   if (rows < 1) return hipErrorInvalidValue;
   const dim3 grid((unsigned)((src.nx + PAIR_W - 1) / PAIR_W), (unsigned)((src.ny + rows - 1) / rows));
-  if (pow) {
-    if (logda) hipLaunchKernelGGL((k_step2<true, true>), grid, dim3(TILE), 0, s, src, dst, rows);
-    else hipLaunchKernelGGL((k_step2<true, false>), grid, dim3(TILE), 0, s, src, dst, rows);
+#define PM_PAIR(POW, LOG, SR) hipLaunchKernelGGL((k_step2<POW, LOG, SR>), grid, dim3(TILE), 0, s, src, dst, rows)
+  if (src.sr) {
+    if (pow) { if (logda) PM_PAIR(true, true, true); else PM_PAIR(true, false, true); }
+    else { if (logda) PM_PAIR(false, true, true); else PM_PAIR(false, false, true); }
   } else {
-    if (logda) hipLaunchKernelGGL((k_step2<false, true>), grid, dim3(TILE), 0, s, src, dst, rows);
-    else hipLaunchKernelGGL((k_step2<false, false>), grid, dim3(TILE), 0, s, src, dst, rows);
+    if (pow) { if (logda) PM_PAIR(true, true, false); else PM_PAIR(true, false, false); }
+    else { if (logda) PM_PAIR(false, true, false); else PM_PAIR(false, false, false); }
   }
+#undef PM_PAIR
   return hipGetLastError();
 }
 
@@ -526,15 +547,25 @@ hipError_t launch_step_oop(const KParams<T>& src, const KParams<T>& dst, const L
                            bool pow, bool logda) {
   if (!(L.step_w == 64 || L.step_w == 128 || L.step_w == 256) || L.step_w > TILE) return hipErrorInvalidValue;
   dim3 grid(L.step_ntiles), block(L.step_w);
-#define PM_OOP(ODD, POW, LOG) \
-  hipLaunchKernelGGL((k_step_oop<T, ODD, POW, LOG>), grid, block, 0, L.stream, src, dst, L.step_tiles_x)
-  if (parity) {
-    if (pow) { if (logda) PM_OOP(true, true, true); else PM_OOP(true, true, false); }
-    else { if (logda) PM_OOP(true, false, true); else PM_OOP(true, false, false); }
-  } else {
-    if (pow) { if (logda) PM_OOP(false, true, true); else PM_OOP(false, true, false); }
-    else { if (logda) PM_OOP(false, false, true); else PM_OOP(false, false, false); }
+#define PM_OOP(ODD, POW, LOG, SR) \
+  hipLaunchKernelGGL((k_step_oop<T, ODD, POW, LOG, SR>), grid, block, 0, L.stream, src, dst, L.step_tiles_x)
+#define PM_OOP_ALL(SR)                                                                              \
+  if (parity) {                                                                                     \
+    if (pow) { if (logda) PM_OOP(true, true, true, SR); else PM_OOP(true, true, false, SR); }         \
+    else { if (logda) PM_OOP(true, false, true, SR); else PM_OOP(true, false, false, SR); }          \
+  } else {                                                                                          \
+    if (pow) { if (logda) PM_OOP(false, true, true, SR); else PM_OOP(false, true, false, SR); }      \
+    else { if (logda) PM_OOP(false, false, true, SR); else PM_OOP(false, false, false, SR); }       \
   }
+  bool done = false;
+  if constexpr (std::is_same<T, float>::value) {
+    if (src.sr) {
+      PM_OOP_ALL(true)
+      done = true;
+    }
+  }
+  if (!done) { PM_OOP_ALL(false) }
+#undef PM_OOP_ALL
 #undef PM_OOP
   return hipGetLastError();
 }

@@ -88,3 +88,15 @@ def test_fp32_at_the_oracle_step(gold):
     e32 = errors(cav, gold)
     print(f"FP32 at S*: {e32}", flush=True)
     assert max(e32.values()) <= 1e-3
+
+
+def test_fp32_stochastic_rounding_meets_the_bar(gold):
+    """FP32 storage and arithmetic with stochastically rounded population
+    updates (PM_ROUND_STOCHASTIC), run for exactly S* steps: the bias that
+    round-to-nearest storage accumulates in the slow modes is gone, and every
+    field and Nu meet the 1e-4 FP32 bar."""
+    cav = P.Cavity(N, dtype="fp32", rounding="stochastic", **PHYS)
+    cav.step(int(gold["steps"]))
+    e = errors(cav, gold)
+    print(f"FP32 stochastic rounding at S*: {e}", flush=True)
+    assert max(e.values()) <= 1e-4

@@ -41,6 +41,25 @@ def test_cavity_64_newtonian_20000_steps(dtype):
     assert max(errs.values()) <= TOL[dtype] and dnu <= TOL[dtype]
 
 
+def test_cavity_64_fp32_stochastic_rounding():
+    """The 64x64 cavity of the first test in FP32 with stochastically rounded
+    updates: within the FP32 bar of the oracle after 20000 steps, and
+    deterministic (two runs bitwise equal)."""
+    runs = []
+    for _ in range(2):
+        cav = gpu_for(64, dtype="fp32", rounding="stochastic", **CFG0)
+        cav.step(20000)
+        runs.append(cav)
+    orc = oracle_for(64, **CFG0).step(20000)
+    errs = compare_fields(runs[0], orc)
+    dnu = compare_nu(runs[0], orc)
+    log("fp32 stochastic", errs, dnu)
+    assert max(errs.values()) <= 1e-4 and dnu <= 1e-4
+    fa, ga = runs[0].populations(torch.float32)
+    fb, gb = runs[1].populations(torch.float32)
+    assert torch.equal(fa, fb) and torch.equal(ga, gb)
+
+
 RANDOM_CASES = [
     dict(n=1.0, Da=0.1, Ra=1e3, Pr=10.0, eps=0.6),
     dict(n=0.6, Da=1e-3, Ra=1e5, Pr=10.0, eps=0.6),
@@ -359,8 +378,9 @@ PAIR_SIZES = [(8, 8), (33, 21), (252, 70), (300, 130), (520, 67)]
 
 
 @pytest.mark.parametrize("size", PAIR_SIZES)
-@pytest.mark.parametrize("n,logda", [(1.0, False), (0.6, False), (0.8, True)])
-def test_two_step_kernel_equals_single_steps(size, n, logda):
+@pytest.mark.parametrize("n,logda,rounding", [(1.0, False, "nearest"), (0.6, False, "nearest"),
+                                              (0.8, True, "nearest"), (0.6, False, "stochastic")])
+def test_two_step_kernel_equals_single_steps(size, n, logda, rounding):
     """The two-step kernel (forced with PM_STEP_PAIR: by default it runs only
     on grids large enough to fill the GPU) against the single-step kernel:
     both must give the same populations bit for bit -- on grids narrower and
@@ -368,7 +388,7 @@ def test_two_step_kernel_equals_single_steps(size, n, logda):
     random state, and across a graph-replayed run (k >= 128, starting at an
     odd step count)."""
     nx, ny = size
-    kw = dict(n=n, Da=1e-2, Ra=1e5, Pr=10.0, eps=0.6)
+    kw = dict(n=n, Da=1e-2, Ra=1e5, Pr=10.0, eps=0.6, rounding=rounding)
     ld = inputs.logda_field(max(nx, ny), seed=2)[:ny, :nx].copy() if logda else None
     a = gpu_for(nx, ny, dtype="fp32", logda=ld, step_kernel="pair", **kw)
     b = gpu_for(nx, ny, dtype="fp32", logda=ld, step_kernel="single", **kw)

@@ -131,6 +131,24 @@ def test_sweep_with_smallest_grids(tile):
         assert torch.equal(fa, fb) and torch.equal(ga, gb), i
 
 
+def test_sweep_with_stochastic_rounding_equals_cases_run_alone():
+    """FP32 cases with stochastically rounded updates: the sweep kernel draws
+    the same dither as the single-case kernel, so every case stays bitwise
+    equal to the case run alone."""
+    cases = [dict(c, dtype="fp32", rounding="stochastic") for c in CASES]
+    sw = P.Sweep(cases, tile=(128, 2))
+    sw.step(301)
+    for i, kw in enumerate(cases):
+        kw = dict(kw)
+        nx = kw.pop("nx")
+        ny = kw.pop("ny", None)
+        alone = P.Cavity(nx, ny, **kw)
+        alone.step(301)
+        fa, ga = alone.populations(torch.float32)
+        fb, gb = sw.case(i).populations(torch.float32)
+        assert torch.equal(fa, fb) and torch.equal(ga, gb), i
+
+
 def test_unsupported_tile_shape_is_rejected():
     sw = P.Sweep([dict(CASES[0], dtype="fp32")])
     for bad in ((32, 1), (256, 2), (96, 1), (64, 3)):
@@ -194,3 +212,4 @@ def test_27_case_sweep_small_cases_match_oracle_at_5000_steps(dtype):
         worst = max(max(errs.values()), dnu)
         print(f"{dtype} case {i} {cs[i]}: {errs}, dNu {dnu:.2e}, oracle spread {spread:.2e}", flush=True)
         assert worst <= max(bar, 3 * spread), (i, worst, spread)
+
