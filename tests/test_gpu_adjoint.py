@@ -129,6 +129,31 @@ def test_nusselt_autograd_function():
     assert n.grad.item() == gn and Ra.grad.item() == gRa
 
 
+def test_adjoint_on_a_stochastically_rounded_forward():
+    """An FP32 forward with stochastically rounded updates: the checkpointed
+    forward equals the plain run bit for bit (the segment replays draw the same
+    dither), and the gradients agree with those of the round-to-nearest forward
+    to 1e-3 (the two trajectories differ only by rounding)."""
+    N, T = 24, 120
+    ld = inputs.logda_field(N, seed=4)
+    kw = dict(PHYS, n=1.0, Ra=1e4)
+    runs = {}
+    for rounding in ("nearest", "stochastic"):
+        cav = P.Cavity(N, dtype="fp32", logda=torch.from_numpy(ld), rounding=rounding, **kw)
+        adj = P.Adjoint(cav, T)
+        J = adj.forward()
+        gld, gn, gRa = adj.backward()
+        plain = P.Cavity(N, dtype="fp32", logda=torch.from_numpy(ld), rounding=rounding, **kw)
+        plain.step(T)
+        assert J == plain.nu()
+        runs[rounding] = (J, gld.cpu().numpy(), gn, gRa)
+    (Ja, ga, na, ra), (Jb, gb, nb, rb) = runs["nearest"], runs["stochastic"]
+    print(f"J {Ja:.9f} / {Jb:.9f}, dJ/dn {na:.6e} / {nb:.6e}", flush=True)
+    assert abs(Ja - Jb) <= 1e-5 * abs(Ja)
+    assert np.abs(ga - gb).max() <= 1e-3 * np.abs(ga).max()
+    assert nb == pytest.approx(na, rel=1e-3) and rb == pytest.approx(ra, rel=1e-3)
+
+
 # The 256 x 256 adjoint workload: per-cell log10 Da ~ U[-3, -1] (seed 0),
 # J = Nu_bar after 5000 steps from rest, gradients with respect to 16 seeded
 # cells, n and Ra.

@@ -299,7 +299,8 @@ def test_full_size_4096_fp32_sampled():
     assert np.all(Ug[100:-100, 100:-100] == 0.0) and np.all(Tg[100:-100, 100:-100] == 0.5)
 
 
-def test_full_size_4096_fp32_random_state():
+@pytest.mark.parametrize("rounding", ["nearest", "stochastic"])
+def test_full_size_4096_fp32_random_state(rounding):
     """The same 4096^2 workload and launch configuration, started from a random
     non-equilibrium state so that every node moves and the viscosity solve
     runs on the power-law branch everywhere: all fields, every node, against
@@ -310,8 +311,8 @@ def test_full_size_4096_fp32_random_state():
     kw = dict(n=0.8, Da=1e-2, Ra=1e5, Pr=10.0, eps=0.6)
     N = 4096
     f0, g0 = inputs.random_state(N, N, seed=11, amp=0.02, amp_T=0.1)
-    log("case: 4096^2 fp32 from a random state (seed 11)", kw)
-    cav = gpu_for(N, dtype="fp32", **kw)
+    log("case: 4096^2 fp32 from a random state (seed 11)", kw, rounding)
+    cav = gpu_for(N, dtype="fp32", rounding=rounding, **kw)
     cav.set_populations(torch.from_numpy(f0), torch.from_numpy(g0))
     orc = oracle_for(N, **kw)
     orc.set_state(f0, g0)
