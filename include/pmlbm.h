@@ -107,7 +107,7 @@ typedef struct {
                              state).  Stochastic rounding adds each node's update to its stored
                              populations with a +-1/2-ulp dither from a hash of the node and its
                              inputs: deterministic, the same in every kernel, unbiased, and about
-                             50% more time per step at 4096^2.  PM_EINVAL with FP64. */
+                             20% more time per step at 4096^2.  PM_EINVAL with FP64. */
 } pm_params;
 
 /* Lattice values derived from pm_params (read-only description). */
