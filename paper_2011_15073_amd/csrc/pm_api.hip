@@ -713,6 +713,7 @@ struct pm_sweep {
   std::vector<int> ntiles, tile_base;
   int total_tiles;
   int tile_w, tile_h;   // sweep tile: tile_w columns by tile_h rows (pm_sweep_set_tile)
+  bool any_sr;          // some case rounds stochastically (PM_ROUND_STOCHASTIC)
   void* d_cases;        // SweepCase<T>[ncases]
   int2* d_sched;        // schedule entries (case, tile)
   int* d_live;          // 1 while the case still runs
@@ -819,10 +820,10 @@ hipError_t sweep_enqueue_chunk(pm_sweep* s, hipStream_t st, int64_t chunk, int p
     const int par = (int)((parity0 + t) & 1);
     if (s->dtype == PM_FP64)
       e = pm::launch_step_multi<double>((const pm::SweepCase<double>*)s->d_cases, s->d_sched, s->d_live,
-                                        s->total_tiles, par, s->tile_w, s->tile_h, st);
+                                        s->total_tiles, par, s->tile_w, s->tile_h, s->any_sr, st);
     else
       e = pm::launch_step_multi<float>((const pm::SweepCase<float>*)s->d_cases, s->d_sched, s->d_live,
-                                       s->total_tiles, par, s->tile_w, s->tile_h, st);
+                                       s->total_tiles, par, s->tile_w, s->tile_h, s->any_sr, st);
   }
   if (e != hipSuccess) return e;
   const int par_end = (int)((parity0 + chunk) & 1);
@@ -945,6 +946,9 @@ int pm_sweep_create(const pm_params* cases, int ncases, void* dev_ws, size_t ws_
   s->stream = (hipStream_t)hip_stream;
   s->tile_w = pm::TILE;
   s->tile_h = 1;
+  s->any_sr = false;
+  for (int i = 0; i < ncases; ++i)
+    if (cases[i].rounding == PM_ROUND_STOCHASTIC) s->any_sr = true;
   char* base = (char*)dev_ws;
   s->d_cases = base + L.off_cases;
   s->d_sched = (int2*)(base + L.off_sched);
@@ -1085,10 +1089,10 @@ int pm_sweep_step(pm_sweep* s, int64_t k) {
     const int par = (int)((s->gsteps + t) & 1);
     if (s->dtype == PM_FP64)
       e = pm::launch_step_multi<double>((const pm::SweepCase<double>*)s->d_cases, s->d_sched, s->d_live,
-                                        s->total_tiles, par, s->tile_w, s->tile_h, s->stream);
+                                        s->total_tiles, par, s->tile_w, s->tile_h, s->any_sr, s->stream);
     else
       e = pm::launch_step_multi<float>((const pm::SweepCase<float>*)s->d_cases, s->d_sched, s->d_live,
-                                       s->total_tiles, par, s->tile_w, s->tile_h, s->stream);
+                                       s->total_tiles, par, s->tile_w, s->tile_h, s->any_sr, s->stream);
   }
   if (e != hipSuccess) return sweep_fail(s, PM_EDEVICE, "pm_sweep_step: %s", hipGetErrorString(e));
   // live cases advance together; the per-case counters follow on the device

@@ -138,13 +138,14 @@ template <typename T>
 hipError_t launch_set_logda(const KParams<T>& p, const Launch& L, T* dst, const void* src,
                             int in_fp64);
 // Sweep tiles are tw columns by th rows: tw in {64, 128, 256}, th in {1, 2, 4},
-// tw * th <= TILE threads (a wave then lies within one grid row).
+// tw * th <= TILE threads (a wave then lies within one grid row).  any_sr:
+// some case of the sweep rounds stochastically.
 inline bool sweep_tile_ok(int tw, int th) {
   return (tw == 64 || tw == 128 || tw == 256) && (th == 1 || th == 2 || th == 4) && tw * th <= TILE;
 }
 template <typename T>
 hipError_t launch_step_multi(const SweepCase<T>* cases, const int2* sched, const int* live,
-                             int nsched, int parity, int tw, int th, hipStream_t s);
+                             int nsched, int parity, int tw, int th, bool any_sr, hipStream_t s);
 template <typename T>
 hipError_t launch_resid_multi(const SweepCase<T>* cases, int ncases, const int2* sched, int* live,
                               int nsched, int parity, int tw, int th, double* partial, SweepStatus* st,

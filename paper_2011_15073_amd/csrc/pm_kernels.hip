@@ -177,8 +177,10 @@ __global__ __launch_bounds__(TILE) void k_step2(KParams<float> src, KParams<floa
 // t % tw, row t / tw of the tile, so every wave lies within one grid row.
 // Each case runs the same per-node body as the single-case kernel, so a case
 // advanced here is bitwise identical to the same case advanced alone,
-// whatever the tile shape.
-template <typename T, bool ODD>
+// whatever the tile shape.  SR_ANY: some case rounds stochastically (FP32
+// only); without it the kernel carries no stochastic-rounding branch, which
+// would cost round-to-nearest sweeps registers and occupancy.
+template <typename T, bool ODD, bool SR_ANY>
 __global__ __launch_bounds__(TILE) void k_step_multi(const SweepCase<T>* __restrict__ cases,
                                                      const int2* __restrict__ sched,
                                                      const int* __restrict__ live, int tw, int th) {
@@ -189,7 +191,7 @@ __global__ __launch_bounds__(TILE) void k_step_multi(const SweepCase<T>* __restr
   const int lx = (int)threadIdx.x % tw, j = ty * th + (int)threadIdx.x / tw;
   if (j >= c.p.ny) return;  // whole waves
   const int i0 = (e.y - ty * c.tiles_x) * tw;
-  if constexpr (std::is_same<T, float>::value) {
+  if constexpr (SR_ANY && std::is_same<T, float>::value) {
     if (c.p.sr) {
       if (c.pow) step_tile<T, ODD, true, false, true>(c.p, c.p, i0, j, lx);
       else step_tile<T, ODD, false, false, true>(c.p, c.p, i0, j, lx);
@@ -572,12 +574,21 @@ hipError_t launch_step_oop(const KParams<T>& src, const KParams<T>& dst, const L
 
 template <typename T>
 hipError_t launch_step_multi(const SweepCase<T>* cases, const int2* sched, const int* live,
-                             int nsched, int parity, int tw, int th, hipStream_t s) {
+                             int nsched, int parity, int tw, int th, bool any_sr, hipStream_t s) {
   if (!sweep_tile_ok(tw, th)) return hipErrorInvalidValue;
-  if (parity)
-    hipLaunchKernelGGL((k_step_multi<T, true>), dim3(nsched), dim3(tw * th), 0, s, cases, sched, live, tw, th);
-  else
-    hipLaunchKernelGGL((k_step_multi<T, false>), dim3(nsched), dim3(tw * th), 0, s, cases, sched, live, tw, th);
+#define PM_MULTI(ODD, SR) \
+  hipLaunchKernelGGL((k_step_multi<T, ODD, SR>), dim3(nsched), dim3(tw * th), 0, s, cases, sched, live, tw, th)
+  bool sr = false;
+  if constexpr (std::is_same<T, float>::value) {
+    sr = any_sr;
+    if (sr) {
+      if (parity) PM_MULTI(true, true); else PM_MULTI(false, true);
+    }
+  }
+  if (!sr) {
+    if (parity) PM_MULTI(true, false); else PM_MULTI(false, false);
+  }
+#undef PM_MULTI
   return hipGetLastError();
 }
 
@@ -727,7 +738,7 @@ hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, hipStream
                                         const void*, int);                                      \
   template hipError_t launch_set_logda<T>(const KParams<T>&, const Launch&, T*, const void*, int); \
   template hipError_t launch_step_multi<T>(const SweepCase<T>*, const int2*, const int*, int, int, \
-                                           int, int, hipStream_t);                                \
+                                           int, int, bool, hipStream_t);                          \
   template hipError_t launch_resid_multi<T>(const SweepCase<T>*, int, const int2*, int*, int, int, \
                                             int, int, double*, SweepStatus*, int64_t, double,     \
                                             int64_t, hipStream_t);
