@@ -98,8 +98,9 @@ typedef struct {
   int32_t step_kernel;    /* PM_STEP_AUTO (default), PM_STEP_SINGLE or PM_STEP_PAIR.  Both
                              kernels give the same populations bit for bit; the two-step
                              kernel needs a second population region in the workspace
-                             (pm_workspace_bytes accounts for it).  PM_STEP_PAIR with FP64
-                             or a periodic axis is PM_EINVAL. */
+                             (pm_workspace_bytes accounts for it).  PM_STEP_PAIR with FP64,
+                             a periodic axis or ny > 24 * 65535 is PM_EINVAL (PM_STEP_AUTO
+                             then takes the single-step kernel). */
   int32_t rounding;       /* PM_ROUND_NEAREST (default) or PM_ROUND_STOCHASTIC, FP32 only.  Near a
                              steady flow, round-to-nearest storage makes the same rounding every
                              step, and the cavity's slowly decaying modes turn that fixed pattern

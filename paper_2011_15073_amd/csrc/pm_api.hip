@@ -82,6 +82,7 @@ int pair_rows_for(int nx, int ny, int cus) {
   int best = pm::PAIR_R;
   double best_cost = 1e300;
   for (int r = pm::PAIR_R; r >= pm::PAIR_R_MIN; --r) {
+    if ((ny + r - 1) / r > pm::GRID_Y_MAX) break;  // row groups are gridDim.y
     const int64_t wg = strips * ((ny + r - 1) / r);
     const int64_t rounds = (wg + slots - 1) / slots;
     const double fill = (double)wg / (double)(rounds * slots);
@@ -96,6 +97,7 @@ int pair_rows_for(int nx, int ny, int cus) {
 
 bool pair_capable(const pm_params& p) {
   if (!PM_PAIR_STEP || p.dtype != PM_FP32 || p.periodic_x || p.periodic_y) return false;
+  if ((p.ny + pm::PAIR_R - 1) / pm::PAIR_R > pm::GRID_Y_MAX) return false;
   if (p.step_kernel == PM_STEP_PAIR) return true;
   if (p.step_kernel == PM_STEP_SINGLE) return false;
   const int64_t wg = (int64_t)((p.nx + pm::PAIR_W - 1) / pm::PAIR_W) * ((p.ny + pm::PAIR_R - 1) / pm::PAIR_R);
@@ -165,6 +167,8 @@ int map_params(const pm_params& p, pm_lattice& L, char* msg, size_t msglen) {
     return fail("step_kernel must be PM_STEP_AUTO, PM_STEP_SINGLE or PM_STEP_PAIR");
   if (p.step_kernel == PM_STEP_PAIR && (!PM_PAIR_STEP || p.dtype != PM_FP32 || p.periodic_x || p.periodic_y))
     return fail("PM_STEP_PAIR needs FP32 and cavity walls on both axes");
+  if (p.step_kernel == PM_STEP_PAIR && (p.ny + pm::PAIR_R - 1) / pm::PAIR_R > pm::GRID_Y_MAX)
+    return fail("PM_STEP_PAIR: ny too large (more row groups than a launch's y dimension takes)");
   if (p.rounding != PM_ROUND_NEAREST && p.rounding != PM_ROUND_STOCHASTIC)
     return fail("rounding must be PM_ROUND_NEAREST or PM_ROUND_STOCHASTIC");
   if (p.rounding == PM_ROUND_STOCHASTIC && p.dtype != PM_FP32)

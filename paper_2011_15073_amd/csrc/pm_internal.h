@@ -111,6 +111,7 @@ constexpr int PAIR_R_MIN = 16;
 constexpr int PAIR_PER_CU = 3;  // resident workgroups per CU (LDS: 2 x 24 KB each)
 constexpr int64_t PAIR_MIN_WORKGROUPS = 9 * 256;
 constexpr int RED_BLOCKS = 1024; // partial-result slots of the residual
+constexpr int GRID_Y_MAX = 65535; // largest gridDim.y of any launch: taller grids loop over rows
 
 // parity 0: state in natural layout; 1: after an odd number of steps
 template <typename T>

@@ -29,6 +29,7 @@
 // the default caching.
 #include "pm_device.h"
 
+#include <algorithm>
 #include <type_traits>
 
 namespace pm {
@@ -354,19 +355,20 @@ __global__ void k_retire(const SweepCase<T>* __restrict__ cases, int ncases,
 
 template <typename T, bool ODD, bool POW, bool LOGDA, typename O>
 __global__ __launch_bounds__(TILE) void k_fields(KParams<T> p, O* U, O* V, O* th, O* nuo) {
-  const int j = blockIdx.y;
   const int i = blockIdx.x * TILE + threadIdx.x;
   if (i >= p.nx) return;
-  T df[9], dg[5];
-  load_node<T, ODD>(p, i, j, df, dg);
-  T drho, rho, jx, jy, dT, Gx, Gy, nu, ux, uy, invK, invsK, m1, m7, m8;
-  const int k = j * p.nx + i;
-  node_macros<T, POW, LOGDA>(p, k, df, dg, drho, rho, jx, jy, dT, Gx, Gy, nu, ux, uy, invK,
-                             invsK, m1, m7, m8);
-  if (U) U[k] = (O)(ux * p.inv_U);
-  if (V) V[k] = (O)(uy * p.inv_U);
-  if (th) th[k] = (O)(p.T_ref + dT);
-  if (nuo) nuo[k] = (O)nu;
+  for (int j = blockIdx.y; j < p.ny; j += gridDim.y) {
+    T df[9], dg[5];
+    load_node<T, ODD>(p, i, j, df, dg);
+    T drho, rho, jx, jy, dT, Gx, Gy, nu, ux, uy, invK, invsK, m1, m7, m8;
+    const int k = j * p.nx + i;
+    node_macros<T, POW, LOGDA>(p, k, df, dg, drho, rho, jx, jy, dT, Gx, Gy, nu, ux, uy, invK,
+                               invsK, m1, m7, m8);
+    if (U) U[k] = (O)(ux * p.inv_U);
+    if (V) V[k] = (O)(uy * p.inv_U);
+    if (th) th[k] = (O)(p.T_ref + dT);
+    if (nuo) nuo[k] = (O)nu;
+  }
 }
 
 // D2Q9 / D2Q5 rest weights for the absolute <-> shifted conversions.
@@ -381,29 +383,33 @@ __device__ __forceinline__ T w5(int q) {
 
 template <typename T, bool ODD, typename O>
 __global__ __launch_bounds__(TILE) void k_get_pop(KParams<T> p, O* f, O* g) {
-  const int j = blockIdx.y;
   const int i = blockIdx.x * TILE + threadIdx.x;
   if (i >= p.nx) return;
-  T df[9], dg[5];
-  load_node<T, ODD>(p, i, j, df, dg);
-  const int64_t k = (int64_t)j * p.nx + i, n = (int64_t)p.nx * p.ny;
+  const int64_t n = (int64_t)p.nx * p.ny;
+  for (int j = blockIdx.y; j < p.ny; j += gridDim.y) {
+    T df[9], dg[5];
+    load_node<T, ODD>(p, i, j, df, dg);
+    const int64_t k = (int64_t)j * p.nx + i;
 #pragma unroll
-  for (int q = 0; q < 9; ++q) f[q * n + k] = (O)((double)df[q] + (double)w9<T>(q));
+    for (int q = 0; q < 9; ++q) f[q * n + k] = (O)((double)df[q] + (double)w9<T>(q));
 #pragma unroll
-  for (int q = 0; q < 5; ++q) g[q * n + k] = (O)((double)dg[q] + (double)w5<T>(q) * (double)p.T_ref);
+    for (int q = 0; q < 5; ++q) g[q * n + k] = (O)((double)dg[q] + (double)w5<T>(q) * (double)p.T_ref);
+  }
 }
 
 template <typename T, typename I>
 __global__ __launch_bounds__(TILE) void k_set_pop(KParams<T> p, const I* f, const I* g) {
-  const int j = blockIdx.y;
   const int i = blockIdx.x * TILE + threadIdx.x;
   if (i >= p.nx) return;
-  const int64_t k = (int64_t)j * p.nx + i, n = (int64_t)p.nx * p.ny, o = pop_off(p, i, j);
+  const int64_t n = (int64_t)p.nx * p.ny;
+  for (int j = blockIdx.y; j < p.ny; j += gridDim.y) {
+    const int64_t k = (int64_t)j * p.nx + i, o = pop_off(p, i, j);
 #pragma unroll
-  for (int q = 0; q < 9; ++q) p.f[q * p.qs + o] = (T)((double)f[q * n + k] - (double)w9<T>(q));
+    for (int q = 0; q < 9; ++q) p.f[q * p.qs + o] = (T)((double)f[q * n + k] - (double)w9<T>(q));
 #pragma unroll
-  for (int q = 0; q < 5; ++q)
-    p.g[q * p.qs + o] = (T)((double)g[q * n + k] - (double)w5<T>(q) * (double)p.T_ref);
+    for (int q = 0; q < 5; ++q)
+      p.g[q * p.qs + o] = (T)((double)g[q * n + k] - (double)w5<T>(q) * (double)p.T_ref);
+  }
 }
 
 template <typename T, typename I>
@@ -431,7 +437,7 @@ __global__ void k_header(int64_t* dst, int64_t steps, uint64_t tag) {
 // Rows per block: 64, doubled until the block count fits a launch's y extent.
 inline int psi_rows(int ny) {
   int r = 64;
-  while ((ny + r - 1) / r > 65535) r *= 2;
+  while ((ny + r - 1) / r > GRID_Y_MAX) r *= 2;
   return r;
 }
 
@@ -531,6 +537,7 @@ hipError_t launch_step(const KParams<T>& p, const Launch& L, int parity, bool po
 hipError_t launch_step2(const KParams<float>& src, const KParams<float>& dst, hipStream_t s, bool pow,
                         bool logda, int rows) {
   if (rows < 1) return hipErrorInvalidValue;
+  if (rows < 1 || (src.ny + rows - 1) / rows > GRID_Y_MAX) return hipErrorInvalidValue;
   const dim3 grid((unsigned)((src.nx + PAIR_W - 1) / PAIR_W), (unsigned)((src.ny + rows - 1) / rows));
 #define PM_PAIR(POW, LOG, SR) hipLaunchKernelGGL((k_step2<POW, LOG, SR>), grid, dim3(TILE), 0, s, src, dst, rows)
   if (src.sr) {
@@ -633,7 +640,7 @@ hipError_t launch_residual(const KParams<T>& p, const Launch& L, int parity, T* 
 template <typename T>
 hipError_t launch_fields(const KParams<T>& p, const Launch& L, int parity, bool pow, bool logda,
                          void* U, void* V, void* th, void* nu, int out_fp64) {
-  dim3 grid(L.tiles_x, p.ny), block(TILE);
+  dim3 grid(L.tiles_x, std::min(p.ny, GRID_Y_MAX)), block(TILE);
 #define PM_F(ODD, POW, LOG, O)                                                              \
   hipLaunchKernelGGL((k_fields<T, ODD, POW, LOG, O>), grid, block, 0, L.stream, p, (O*)U, \
                      (O*)V, (O*)th, (O*)nu)
@@ -653,7 +660,7 @@ hipError_t launch_fields(const KParams<T>& p, const Launch& L, int parity, bool 
 template <typename T>
 hipError_t launch_get_pop(const KParams<T>& p, const Launch& L, int parity, void* f, void* g,
                           int out_fp64) {
-  dim3 grid(L.tiles_x, p.ny), block(TILE);
+  dim3 grid(L.tiles_x, std::min(p.ny, GRID_Y_MAX)), block(TILE);
   if (parity) {
     if (out_fp64) hipLaunchKernelGGL((k_get_pop<T, true, double>), grid, block, 0, L.stream, p, (double*)f, (double*)g);
     else hipLaunchKernelGGL((k_get_pop<T, true, float>), grid, block, 0, L.stream, p, (float*)f, (float*)g);
@@ -667,7 +674,7 @@ hipError_t launch_get_pop(const KParams<T>& p, const Launch& L, int parity, void
 template <typename T>
 hipError_t launch_set_pop(const KParams<T>& p, const Launch& L, const void* f, const void* g,
                           int in_fp64) {
-  dim3 grid(L.tiles_x, p.ny), block(TILE);
+  dim3 grid(L.tiles_x, std::min(p.ny, GRID_Y_MAX)), block(TILE);
   if (in_fp64)
     hipLaunchKernelGGL((k_set_pop<T, double>), grid, block, 0, L.stream, p, (const double*)f, (const double*)g);
   else

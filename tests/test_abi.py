@@ -108,6 +108,11 @@ def test_step_kernel_choice():
     single = P.workspace_bytes(P.make_params(256, dtype="fp32", step_kernel="single", **kw))
     pair = P.workspace_bytes(P.make_params(256, dtype="fp32", step_kernel="pair", **kw))
     assert auto == single < pair
+    # the two-step kernel's row groups are a launch's y dimension (<= 65535)
+    tall = dict(nx=300, ny=24 * 65535 + 1, dtype="fp32", **kw)
+    with pytest.raises(P.PmError):
+        P.workspace_bytes(P.make_params(step_kernel="pair", **tall))
+    assert P.workspace_bytes(P.make_params(**tall)) == P.workspace_bytes(P.make_params(step_kernel="single", **tall))
     big_auto = P.workspace_bytes(P.make_params(4096, dtype="fp32", **kw))
     big_single = P.workspace_bytes(P.make_params(4096, dtype="fp32", step_kernel="single", **kw))
     assert big_auto >= big_single + 14 * 4096 * 4096 * 4

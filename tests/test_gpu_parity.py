@@ -14,6 +14,8 @@ import numpy as np
 import pytest
 import torch
 
+import oracle as O
+import paper_2011_15073_amd as P
 from paper_2011_15073_amd import inputs
 from pairs import compare_fields, compare_nu, gpu_for, gpu_fields, oracle_for, rel_err
 
@@ -153,6 +155,43 @@ def test_smallest_grids(grid):
             fr, gr = orc.state()
             assert np.abs(fg - fr).max() <= 1e-13 and np.abs(gg - gr).max() <= 1e-13, (grid, ci, orc.steps)
         assert abs(cav.nu() - orc.nu_bar()) <= 1e-12 * max(1.0, abs(orc.nu_bar()))
+
+
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+def test_grid_taller_than_launch_y_dimension(dtype):
+    """A 5 x 70001 grid: more rows than a launch's y dimension takes (65535),
+    so the population copy-in, copy-out and field kernels loop over rows.
+    Populations (FP64, to 1e-13) and fields (U, V, theta, nu) against the
+    oracle after 1, 2 and 5 steps from a random state; the copy-in and
+    copy-out return the state unchanged (FP32: rounded once)."""
+    kw = RANDOM_CASES[1]
+    nx, ny = 5, 70001
+    f0, g0 = inputs.random_state(nx, ny, seed=41, amp=0.05)
+    log("case: 5x70001 random state", dtype, kw)
+    cav = gpu_for(nx, ny, dtype=dtype, **kw)
+    cav.set_populations(torch.from_numpy(f0), torch.from_numpy(g0))
+    fz, gz = (t.cpu().numpy() for t in cav.populations(torch.float64))
+    if dtype == "fp64":
+        assert np.abs(fz - f0).max() <= 1e-15 and np.abs(gz - g0).max() <= 1e-15
+    else:
+        assert np.abs(fz - f0).max() <= 1e-7 and np.abs(gz - g0).max() <= 1e-7
+    orc = oracle_for(nx, ny, **kw)
+    orc.set_state(f0, g0)
+    for k in (1, 1, 3):
+        cav.step(k)
+        orc.step(k)
+        errs = compare_fields(cav, orc)
+        errs["nu"] = rel_err(cav.viscosity(torch.float64).cpu().numpy(), orc.macros()["nu"])
+        if dtype == "fp64":
+            fg, gg = (t.cpu().numpy() for t in cav.populations(torch.float64))
+            fr, gr = orc.state()
+            ef, eg = np.abs(fg - fr).max(), np.abs(gg - gr).max()
+            log("  after", orc.steps, "steps: pop err", ef, eg, errs)
+            assert ef <= 1e-13 and eg <= 1e-13
+            assert max(errs.values()) <= 1e-11
+        else:
+            log("  after", orc.steps, "steps:", errs)
+            assert max(errs.values()) <= 1e-4
 
 
 SIZES = [(8, 8), (33, 33), (96, 96), (257, 40), (300, 37)]
@@ -328,6 +367,81 @@ def test_full_size_4096_fp32_random_state(rounding):
         assert max(errs.values()) <= 1e-4 and dnu <= 1e-4
     del cav
     torch.cuda.empty_cache()
+
+
+def _wall_map(n, m=64):
+    """For each of n indices, the index in an m-wide grid at the same distance
+    from the nearer wall (the first and last m/2); all others map to m/2."""
+    h = m // 2
+    i = np.arange(n)
+    return np.where(i < h, i, np.where(i >= n - h, i - (n - m), h))
+
+
+@pytest.mark.parametrize("dtype", ["fp32", "fp64"])
+def test_largest_grid_from_rest(dtype):
+    """The largest grid the library takes: 32768 x 32767 nodes, just under
+    2^30, with population offsets far past 2^32 elements.  The test runs 16
+    steps from rest (FP32: single steps and two-step passes).  From a uniform
+    rest state with uniform walls, after k steps only nodes within k of the
+    hot and cold walls have moved, and each node's state depends only on its
+    distance to the walls near it.  So the oracle on a 64 x 64 grid with the
+    same lattice constants fixes every node:
+      * corners map to corners;
+      * the rest of each 32-wide border strip maps to the small grid's middle
+        row or column;
+      * everything else is exactly at rest.
+    Also checked: Nu against Eq. (24) over the rows so mapped.
+
+    FP32 bar: 1e-4 of max|X| (as elsewhere).  FP64 bar: 1e-13 absolute in
+    lattice units, the bar the random-state tests put on populations: |dU|
+    U_lb, |dV| U_lb, |dtheta| <= 1e-13.  Sixteen steps from rest the
+    velocities are ~1e-7 of the O(1) populations, so the oracle's FP64
+    rounding of those populations (it stores them unshifted) reaches ~1e-9
+    of max|U|, and a bar relative to max|U| would measure that rounding."""
+    kw = dict(n=0.8, Da=1e-2, Ra=1e5, Pr=10.0, eps=0.6)
+    nx, ny, m, steps = 32768, 32767, 64, 16
+    h = m // 2
+    tol = TOL[dtype]
+    need = P.workspace_bytes(P.make_params(nx, ny, dtype=dtype, **kw)) + 3 * nx * ny * (4 if dtype == "fp32" else 8)
+    free, _ = torch.cuda.mem_get_info()
+    if free < need + (4 << 30):
+        pytest.skip(f"needs {need / 2**30:.0f} GiB of free device memory, {free / 2**30:.0f} GiB free")
+    lat = O.map_physics(O.physics(nx, ny, **kw))
+    lat.nx, lat.ny = m, m
+    S = O.Oracle(lat).step(steps).fields()
+    # the premise: the small grid's middle rows are alike, its middle columns
+    # untouched (a margin of 16 nodes to the 32-node strips)
+    for X in S:
+        assert np.array_equal(X[16:48], np.broadcast_to(X[h], (32, m)))
+        assert np.array_equal(X[:, 16:48], np.broadcast_to(X[:, h:h + 1], (m, 32)))
+    log("case: largest grid", nx, "x", ny, dtype, kw, steps, "steps from rest")
+    cav = gpu_for(nx, ny, dtype=dtype, **kw)
+    cav.step(1)
+    cav.step(steps - 1)
+    assert cav.steps == steps
+    nu_g = cav.nu()
+    G = cav.fields(torch.float32 if dtype == "fp32" else torch.float64)
+    rmap, cmap = _wall_map(ny, m), _wall_map(nx, m)
+    errs = {}
+    for name, X, R in zip(("U", "V", "theta"), G, S):
+        strips = ((X[:, :h], R[rmap][:, :h]), (X[:, -h:], R[rmap][:, -h:]),
+                  (X[:h, :], R[:h][:, cmap]), (X[-h:, :], R[-h:][:, cmap]))
+        e = max(np.abs(x.cpu().double().numpy() - r).max() for x, r in strips)
+        if dtype == "fp32":
+            errs[name] = e / np.abs(R).max()  # relative to max|X|
+        else:
+            errs[name] = e * (lat.U_lb if name != "theta" else 1.0)  # absolute, lattice units
+    inner = [X[h:-h, h:-h] for X in G]
+    assert int(torch.count_nonzero(inner[0])) == 0 and int(torch.count_nonzero(inner[1])) == 0
+    assert bool(torch.all(inner[2] == 0.5))
+    th = S[2]
+    nu_r = float(np.sum(nx * (8.0 - 9.0 * th[rmap, 0] + th[rmap, 1]) / 3.0) / ny)
+    dnu = abs(nu_g - nu_r) / abs(nu_r)
+    log("  fields", errs, "Nu", nu_g, nu_r, dnu)
+    del G, inner, cav
+    torch.cuda.empty_cache()
+    bar = 1e-4 if dtype == "fp32" else 1e-13
+    assert max(errs.values()) <= bar and dnu <= tol
 
 
 def test_stream_function():
