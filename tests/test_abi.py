@@ -116,3 +116,32 @@ def test_step_kernel_choice():
     big_auto = P.workspace_bytes(P.make_params(4096, dtype="fp32", **kw))
     big_single = P.workspace_bytes(P.make_params(4096, dtype="fp32", step_kernel="single", **kw))
     assert big_auto >= big_single + 14 * 4096 * 4096 * 4
+
+
+def _sweep_ws(cases):
+    """pm_sweep_workspace_bytes on a list of pm_params: (status, bytes)."""
+    import ctypes as C
+    arr = (_lib.PmParams * max(1, len(cases)))(*cases)
+    nb = C.c_size_t(0)
+    return _lib.lib.pm_sweep_workspace_bytes(arr, len(cases), C.byref(nb)), nb.value
+
+
+def test_sweep_case_lists_are_validated():
+    """The sweep's host checks (no device needed): 1..4096 cases, one dtype
+    for all, no per-cell log-Da planes, every case valid on its own; the
+    workspace holds every case's own workspace."""
+    kw = dict(n=0.8, Da=1e-2, Ra=1e4, Pr=10.0, eps=0.6)
+    a = P.make_params(128, dtype="fp64", **kw)
+    b = P.make_params(200, 96, dtype="fp64", **kw)
+    rc, one = _sweep_ws([a])
+    assert rc == 0 and one >= P.workspace_bytes(a)
+    rc, two = _sweep_ws([a, b])
+    assert rc == 0 and two >= P.workspace_bytes(a) + P.workspace_bytes(b) and two > one
+    assert _sweep_ws([])[0] == _lib.PM_EINVAL
+    assert _sweep_ws([a] * 4097)[0] == _lib.PM_EINVAL
+    assert _sweep_ws([a, P.make_params(64, dtype="fp32", **kw)])[0] == _lib.PM_EINVAL
+    assert _sweep_ws([a, P.make_params(64, dtype="fp64", has_logda=1, **kw)])[0] == _lib.PM_EINVAL
+    bad = P.make_params(64, dtype="fp64", **kw)
+    bad.eps = 0.0
+    assert _sweep_ws([a, bad])[0] == _lib.PM_EINVAL
+    assert _lib.lib.pm_last_error(None).decode()
