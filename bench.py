@@ -326,6 +326,9 @@ def main():
     ap.add_argument("--rounding", default="nearest", choices=["nearest", "stochastic"],
                     help="rounding of the FP32 population updates (PM_ROUND_*)")
     ap.add_argument("--roofline-steps", type=int, default=400)
+    ap.add_argument("--side", type=int, default=N,
+                    help="grid side of the timed cavity (default 4096, the benchmark workload; other sides "
+                         "report no counter traffic and no CPU baseline)")
     ap.add_argument("--sweep", action="store_true",
                     help="run the 27-case batched-sweep benchmark instead")
     ap.add_argument("--sweep-dtype", default="fp64", choices=["fp32", "fp64"])
@@ -343,8 +346,9 @@ def main():
                     help="nondimensional shear floor of the regularised adjoint (0: exact)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the path is measured on one GPU's share; see the sharding notes)", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the step is measured on one GPU's share of the grid; a multi-GPU slab split is not implemented)",
+              file=sys.stderr)
         sys.exit(2)
 
     if args.sweep:
@@ -364,12 +368,17 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    kind = "single" if args.step_kernel == "single" else "pair"  # "auto" takes the pair kernel at 4096^2
+    S = args.side
+    # the step kernel the library will run: only the two-step kernel needs a
+    # second population region in the workspace
+    pair = (P.workspace_bytes(P.make_params(S, dtype="fp32", step_kernel=args.step_kernel, **PHYS)) >
+            P.workspace_bytes(P.make_params(S, dtype="fp32", step_kernel="single", **PHYS)))
+    kind = "pair" if pair else "single"
     K = KERNELS[kind]
     spl = K["steps_per_launch"]
-    log(f"bench: {N}x{N} fp32 {PHYS}, warmup {args.warmup}, steps {args.steps}, step kernel {args.step_kernel}, "
-        f"rounding {args.rounding}")
-    cav = P.Cavity(N, dtype="fp32", device="cuda:0", step_kernel=args.step_kernel, rounding=args.rounding,
+    log(f"bench: {S}x{S} fp32 {PHYS}, warmup {args.warmup}, steps {args.steps}, step kernel {args.step_kernel} "
+        f"({K['name'].split()[0]}), rounding {args.rounding}")
+    cav = P.Cavity(S, dtype="fp32", device="cuda:0", step_kernel=args.step_kernel, rounding=args.rounding,
                    **PHYS)
     stream = cav.stream
 
@@ -394,7 +403,7 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_per_step = elapsed * 1e3 / args.steps
-    mlups = N * N * args.steps / elapsed / 1e6
+    mlups = S * S * args.steps / elapsed / 1e6
     log(f"bench: {mlups:.1f} MLUPS, {ms_per_step:.4f} ms/step, Nu {nus[-1] if nus else cav.nu():.6f}")
 
     # roofline of the step kernel: back-to-back launches (for the two-step
@@ -410,7 +419,7 @@ def main():
     e1.synchronize()
     per_step_s = e0.elapsed_time(e1) / 1e3 / rs
     launch_s = spl * per_step_s
-    achieved = BYTES_PER_NODE * N * N * spl / launch_s / 1e9
+    achieved = BYTES_PER_NODE * S * S * spl / launch_s / 1e9
     log(f"bench: {K['name'].split()[0]} {launch_s * 1e6:.1f} us/launch ({per_step_s * 1e6:.1f} us/step), "
         f"{achieved:.0f} GB/s algorithmic")
 
@@ -432,7 +441,8 @@ def main():
     del src, dst
     log(f"bench: copy ceiling {copy_gbs:.0f} GB/s")
 
-    traffic = read_traffic(kind) if args.rounding == "nearest" else None  # counters taken with nearest rounding
+    # the counters were taken at 4096^2 with nearest rounding
+    traffic = read_traffic(kind) if args.rounding == "nearest" and S == N else None
     result = {
         "metric": "MLUPS (flow+thermal)",
         "value": round(mlups, 1),
@@ -446,10 +456,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "porous power-law cavity 4096x4096, D2Q9 MRT + D2Q5 MRT, "
+        "config": {"workload": f"porous power-law cavity {S}x{S}, D2Q9 MRT + D2Q5 MRT, "
                                "FP32 AA layout, n=0.8 Da=1e-2 Ra=1e5 Pr=10 eps=0.6, "
                                "Nu + residual on device every 1000 steps",
-                   "nodes": N * N, "steps_timed": args.steps, "step_kernel": args.step_kernel,
+                   "nodes": S * S, "steps_timed": args.steps, "step_kernel": args.step_kernel,
                    "rounding": args.rounding},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -457,11 +467,11 @@ def main():
                      "kernel": K["name"],
                      "steps_per_launch": spl,
                      "us_per_launch": round(launch_s * 1e6, 2),
-                     "algorithmic_bytes_per_launch": BYTES_PER_NODE * N * N * spl,
+                     "algorithmic_bytes_per_launch": BYTES_PER_NODE * S * S * spl,
                      "copy_ceiling_GBps": round(copy_gbs, 1)},
         "nu_bar": nus[-1] if nus else None,
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and S == N:
         del cav
         torch.cuda.empty_cache()
         log("bench: timing the CPU oracle on a bounded sample ...")
