@@ -219,7 +219,9 @@ int pm_copy_probe(const void* src, void* dst, size_t bytes, void* hip_stream);
  * arithmetic is the single-case kernel's, so every case ends bitwise equal to
  * the same case run alone.  All cases must share one dtype; per-cell log-Da
  * planes are not supported; every case steps one step per pass (step_kernel
- * is ignored).  The workspace (caller-owned device memory,
+ * is ignored).  FP32 cases may mix PM_ROUND_NEAREST and PM_ROUND_STOCHASTIC;
+ * a sweep with no stochastic case runs a step kernel compiled without that
+ * branch (fewer registers).  The workspace (caller-owned device memory,
  * 256-byte aligned) holds every case's planes plus the case table,
  * schedule, flags and partial results. */
 typedef struct pm_sweep pm_sweep;
@@ -228,6 +230,9 @@ typedef struct pm_sweep pm_sweep;
 #define PM_ORDER_LARGEST 1    /* case after case, largest case first */
 #define PM_ORDER_INTERLEAVE 2 /* round-robin over the cases, tile by tile */
 
+/* Bytes of device workspace for these cases.  PM_EINVAL (message in
+ * pm_last_error(NULL)) for ncases outside 1..4096, mixed dtypes, a case with
+ * has_logda, or a case that pm_workspace_bytes rejects. */
 int pm_sweep_workspace_bytes(const pm_params* cases, int ncases, size_t* bytes);
 /* Validates every case, creates one context per case on its slice of the
  * workspace (rest state), uploads the case table and the schedule.
