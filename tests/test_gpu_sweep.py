@@ -131,11 +131,16 @@ def test_sweep_with_smallest_grids(tile):
         assert torch.equal(fa, fb) and torch.equal(ga, gb), i
 
 
-def test_sweep_with_stochastic_rounding_equals_cases_run_alone():
+@pytest.mark.parametrize("mix", ["all", "alternate"])
+def test_sweep_with_stochastic_rounding_equals_cases_run_alone(mix):
     """FP32 cases with stochastically rounded updates: the sweep kernel draws
     the same dither as the single-case kernel, so every case stays bitwise
-    equal to the case run alone."""
-    cases = [dict(c, dtype="fp32", rounding="stochastic") for c in CASES]
+    equal to the case run alone.  "alternate" mixes in round-to-nearest
+    cases, which then take the nearest path of the kernel that carries the
+    stochastic branch."""
+    cases = [dict(c, dtype="fp32",
+                  rounding="stochastic" if mix == "all" or i % 2 == 0 else "nearest")
+             for i, c in enumerate(CASES)]
     sw = P.Sweep(cases, tile=(128, 2))
     sw.step(301)
     for i, kw in enumerate(cases):
