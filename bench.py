@@ -51,6 +51,13 @@ KERNELS = {
               (os.path.join(CSRC, "pm_kernels.hip"), r"// ---- two time steps in one pass.*?(?=// ---- )"),
               (os.path.join(CSRC, "pm_kernels.hip"), r"hipError_t launch_step2\(.*?\n}\n"),
               (os.path.join(CSRC, "pm_api.hip"), r"int pair_rows_for\(.*?\n}\n")]),
+    "single_fp64": dict(
+        name="k_step FP64 (one fused stream+collide step per launch, AA pattern in place)", steps_per_launch=1,
+        traffic_file=os.path.join(ROOT, "profiles", "k_step_fp64_4096_traffic.txt"),
+        srcs=[os.path.join(CSRC, "pm_device.h"), os.path.join(CSRC, "pm_internal.h"),
+              (os.path.join(CSRC, "pm_kernels.hip"), r"void k_step\(KParams<T> p.*?\n}\n"),
+              (os.path.join(CSRC, "pm_kernels.hip"), r"hipError_t launch_step\(.*?\n}\n"),
+              (os.path.join(CSRC, "pm_api.hip"), r"int step_width_for\(.*?\n}\n")]),
     "single": dict(
         name="k_step (one fused stream+collide step per launch, AA pattern in place)", steps_per_launch=1,
         traffic_file=os.path.join(ROOT, "profiles", "k_step_fp32_4096_traffic.txt"),
@@ -323,6 +330,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--step-kernel", default="auto", choices=["auto", "single", "pair"],
                     help="step kernel of the cavity (auto: the two-step kernel at 4096^2)")
+    ap.add_argument("--dtype", default="fp32", choices=["fp32", "fp64"],
+                    help="storage and arithmetic of the timed cavity (fp64: the single-step kernel, 224 B per "
+                         "node update)")
     ap.add_argument("--rounding", default="nearest", choices=["nearest", "stochastic"],
                     help="rounding of the FP32 population updates (PM_ROUND_*)")
     ap.add_argument("--roofline-steps", type=int, default=400)
@@ -368,17 +378,18 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    S = args.side
-    # the step kernel the library will run: only the two-step kernel needs a
-    # second population region in the workspace
-    pair = (P.workspace_bytes(P.make_params(S, dtype="fp32", step_kernel=args.step_kernel, **PHYS)) >
-            P.workspace_bytes(P.make_params(S, dtype="fp32", step_kernel="single", **PHYS)))
-    kind = "pair" if pair else "single"
+    S, dt = args.side, args.dtype
+    # the step kernel the library will run: only the two-step kernel (FP32)
+    # needs a second population region in the workspace
+    pair = (P.workspace_bytes(P.make_params(S, dtype=dt, step_kernel=args.step_kernel, **PHYS)) >
+            P.workspace_bytes(P.make_params(S, dtype=dt, step_kernel="single", **PHYS)))
+    kind = ("pair" if pair else "single") + ("_fp64" if dt == "fp64" else "")
     K = KERNELS[kind]
     spl = K["steps_per_launch"]
-    log(f"bench: {S}x{S} fp32 {PHYS}, warmup {args.warmup}, steps {args.steps}, step kernel {args.step_kernel} "
+    bpn = BYTES_PER_NODE * (2 if dt == "fp64" else 1)
+    log(f"bench: {S}x{S} {dt} {PHYS}, warmup {args.warmup}, steps {args.steps}, step kernel {args.step_kernel} "
         f"({K['name'].split()[0]}), rounding {args.rounding}")
-    cav = P.Cavity(S, dtype="fp32", device="cuda:0", step_kernel=args.step_kernel, rounding=args.rounding,
+    cav = P.Cavity(S, dtype=dt, device="cuda:0", step_kernel=args.step_kernel, rounding=args.rounding,
                    **PHYS)
     stream = cav.stream
 
@@ -419,7 +430,7 @@ def main():
     e1.synchronize()
     per_step_s = e0.elapsed_time(e1) / 1e3 / rs
     launch_s = spl * per_step_s
-    achieved = BYTES_PER_NODE * S * S * spl / launch_s / 1e9
+    achieved = bpn * S * S * spl / launch_s / 1e9
     log(f"bench: {K['name'].split()[0]} {launch_s * 1e6:.1f} us/launch ({per_step_s * 1e6:.1f} us/step), "
         f"{achieved:.0f} GB/s algorithmic")
 
@@ -454,10 +465,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64" if dt == "fp64" else "f32",
         "data": "synthetic",
         "config": {"workload": f"porous power-law cavity {S}x{S}, D2Q9 MRT + D2Q5 MRT, "
-                               "FP32 AA layout, n=0.8 Da=1e-2 Ra=1e5 Pr=10 eps=0.6, "
+                               f"{dt.upper()} AA layout, n=0.8 Da=1e-2 Ra=1e5 Pr=10 eps=0.6, "
                                "Nu + residual on device every 1000 steps",
                    "nodes": S * S, "steps_timed": args.steps, "step_kernel": args.step_kernel,
                    "rounding": args.rounding},
@@ -467,7 +478,7 @@ def main():
                      "kernel": K["name"],
                      "steps_per_launch": spl,
                      "us_per_launch": round(launch_s * 1e6, 2),
-                     "algorithmic_bytes_per_launch": BYTES_PER_NODE * S * S * spl,
+                     "algorithmic_bytes_per_launch": bpn * S * S * spl,
                      "copy_ceiling_GBps": round(copy_gbs, 1)},
         "nu_bar": nus[-1] if nus else None,
     }
