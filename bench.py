@@ -51,6 +51,13 @@ KERNELS = {
               (os.path.join(CSRC, "pm_kernels.hip"), r"// ---- two time steps in one pass.*?(?=// ---- )"),
               (os.path.join(CSRC, "pm_kernels.hip"), r"hipError_t launch_step2\(.*?\n}\n"),
               (os.path.join(CSRC, "pm_api.hip"), r"int pair_rows_for\(.*?\n}\n")]),
+    "pair_sr": dict(
+        name="k_step2 SR (two fused steps per launch, stochastically rounded updates)", steps_per_launch=2,
+        traffic_file=os.path.join(ROOT, "profiles", "k_step2_fp32sr_4096_traffic.txt"),
+        srcs=[os.path.join(CSRC, "pm_device.h"), os.path.join(CSRC, "pm_internal.h"),
+              (os.path.join(CSRC, "pm_kernels.hip"), r"// ---- two time steps in one pass.*?(?=// ---- )"),
+              (os.path.join(CSRC, "pm_kernels.hip"), r"hipError_t launch_step2\(.*?\n}\n"),
+              (os.path.join(CSRC, "pm_api.hip"), r"int pair_rows_for\(.*?\n}\n")]),
     "single_fp64": dict(
         name="k_step FP64 (one fused stream+collide step per launch, AA pattern in place)", steps_per_launch=1,
         traffic_file=os.path.join(ROOT, "profiles", "k_step_fp64_4096_traffic.txt"),
@@ -384,6 +391,8 @@ def main():
     pair = (P.workspace_bytes(P.make_params(S, dtype=dt, step_kernel=args.step_kernel, **PHYS)) >
             P.workspace_bytes(P.make_params(S, dtype=dt, step_kernel="single", **PHYS)))
     kind = ("pair" if pair else "single") + ("_fp64" if dt == "fp64" else "")
+    if args.rounding == "stochastic" and kind + "_sr" in KERNELS:
+        kind += "_sr"
     K = KERNELS[kind]
     spl = K["steps_per_launch"]
     bpn = BYTES_PER_NODE * (2 if dt == "fp64" else 1)
@@ -452,8 +461,8 @@ def main():
     del src, dst
     log(f"bench: copy ceiling {copy_gbs:.0f} GB/s")
 
-    # the counters were taken at 4096^2 with nearest rounding
-    traffic = read_traffic(kind) if args.rounding == "nearest" and S == N else None
+    # counters were taken at 4096^2, with nearest rounding unless the kernel entry is a stochastic one
+    traffic = read_traffic(kind) if S == N and (args.rounding == "nearest" or kind.endswith("_sr")) else None
     result = {
         "metric": "MLUPS (flow+thermal)",
         "value": round(mlups, 1),
