@@ -145,3 +145,26 @@ def test_sweep_case_lists_are_validated():
     bad.eps = 0.0
     assert _sweep_ws([a, bad])[0] == _lib.PM_EINVAL
     assert _lib.lib.pm_last_error(None).decode()
+
+
+def test_adjoint_workspace_checks():
+    """pm_adjoint_workspace_bytes (no device needed): the workspace holds
+    ceil(T / C) state checkpoints, the replay slots and two FP64 adjoint
+    states; T >= 1, 1 <= C <= T, cavity walls, the nu clamp and no extra body
+    force are required."""
+    import ctypes as C
+
+    def ws(p, T, Cc):
+        nb = C.c_size_t(0)
+        return _lib.lib.pm_adjoint_workspace_bytes(C.byref(p), T, Cc, C.byref(nb)), nb.value
+
+    kw = dict(n=0.8, Da=1e-2, Ra=1e4, Pr=10.0, eps=0.6, dtype="fp32", has_logda=1)
+    p = P.make_params(48, 40, **kw)
+    rc, nb = ws(p, 100, 10)
+    assert rc == 0 and nb >= 2 * 14 * 48 * 40 * 8 + 10 * 14 * 48 * 40 * 4
+    assert ws(p, 100, 10)[1] < ws(p, 100, 1)[1]  # 100 checkpoints against 10
+    for T, Cc in ((0, 1), (10, 0), (10, 11)):
+        assert ws(p, T, Cc)[0] == _lib.PM_EINVAL
+    for bad in (dict(periodic_x=1), dict(clamp_mode=1), dict(gx=1e-6)):
+        assert ws(P.make_params(48, 40, **dict(kw, **bad)), 100, 10)[0] == _lib.PM_EINVAL
+    assert _lib.lib.pm_last_error(None).decode()
