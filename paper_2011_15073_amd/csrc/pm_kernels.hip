@@ -536,7 +536,6 @@ hipError_t launch_step(const KParams<T>& p, const Launch& L, int parity, bool po
 
 hipError_t launch_step2(const KParams<float>& src, const KParams<float>& dst, hipStream_t s, bool pow,
                         bool logda, int rows) {
-  if (rows < 1) return hipErrorInvalidValue;
   if (rows < 1 || (src.ny + rows - 1) / rows > GRID_Y_MAX) return hipErrorInvalidValue;
   const dim3 grid((unsigned)((src.nx + PAIR_W - 1) / PAIR_W), (unsigned)((src.ny + rows - 1) / rows));
 #define PM_PAIR(POW, LOG, SR) hipLaunchKernelGGL((k_step2<POW, LOG, SR>), grid, dim3(TILE), 0, s, src, dst, rows)
