@@ -33,7 +33,6 @@
  *
  * Parity unpinned (nothing outside this file fixes them; the tests pin only
  * their self-consistency and the limits that hold for any choice):
- *   - orc_run_to_steady, the stopping step of the residual loop;
  *   - the D2Q5 higher-moment rates sT_e, sT_nu (every thermal pin holds for
  *     any value);
  *   - the choice of the provisional velocity inside the strain rate (Eq. 22);

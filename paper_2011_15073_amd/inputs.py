@@ -6,6 +6,8 @@ Recipes (numpy.random.default_rng):
     per case in itertools.product(n, Da, Ra) order;
   * per-cell log10(Da) field: rng(seed).uniform(-3, -1, (N, N)), float64;
   * finite-difference probe cells: rng(seed + 1).choice(N*N, 16, replace=False);
+  * smooth perturbation direction of the log10(Da) field: rng(seed) normal
+    coefficients of cos(pi a x) cos(pi b y), a, b in 0..2;
   * random population states (parity tests): rest weights times
     (1 + amp * standard normal), thermal weights times (T0 + amp_T * normal).
 """
@@ -44,3 +46,17 @@ def random_state(nx, ny, seed, amp=0.05, T0=0.5, amp_T=0.2):
     f = W9[:, None, None] * (1 + amp * rng.standard_normal((9, ny, nx)))
     g = W5[:, None, None] * (T0 + amp_T * rng.standard_normal((5, ny, nx)))
     return f, g
+
+
+def smooth_direction(N, seed=5):
+    """A smooth whole-field perturbation direction [N, N] for directional
+    finite differences of the log10(Da) field: the nine products
+    cos(pi a x) cos(pi b y), a, b in 0..2, x = i / N, y = j / N, with standard
+    normal coefficients drawn in (a, b) row-major order."""
+    rng = np.random.default_rng(seed)
+    y, x = np.mgrid[0:N, 0:N] / N
+    w = np.zeros((N, N))
+    for a in range(3):
+        for b in range(3):
+            w = w + rng.standard_normal() * np.cos(np.pi * a * x) * np.cos(np.pi * b * y)
+    return w

@@ -237,3 +237,36 @@ def test_physics_mapping_reproduces_groups():
     assert Kc / (L.alpha ** (2 - 0.6) * N ** (2 * (0.6 - 1))) == pytest.approx(10.0, rel=1e-12)
     with pytest.raises(ValueError):
         O.map_physics(O.physics(64, eps=1.5))
+
+
+@pytest.mark.parametrize("npow", [0.6, 1.4])
+@pytest.mark.parametrize("g1,g2", [(0.3, 30.0), (0.01, 1e6)])
+def test_viscosity_with_shear_rate_thresholds(npow, g1, g2):
+    """PM_CLAMP_GAMMA (clamp_mode 1): Eq. (21) with the shear-rate thresholds
+    gamma1, gamma2 made continuous, nu = nu0 clamp(gamma*, gamma1, gamma2)^(n-1),
+    gamma* = (N / U_lb) |gamma| the nondimensional shear rate.  Checked at
+    states on both sides of each threshold (the paper's 0.01 and 1e6, and a
+    narrower pair that the sampled shear rates straddle on both ends)."""
+    N = 64
+    lat = O.map_physics(O.physics(N, n=npow, Ra=1e5, Pr=10.0, eps=0.8, clamp_mode=1,
+                                  nu_lo=g1, nu_hi=g2))
+    U = 0.1 / math.sqrt(3.0)
+    assert lat.gamma_scale == pytest.approx(N / U, rel=1e-15)
+    nu0 = 10.0 / math.sqrt(1e5) ** (2 - npow) * U * N  # Eq. (21)'s nu0 in lattice units
+    assert lat.nu0 == pytest.approx(nu0, rel=1e-14)
+    rng = np.random.default_rng(21)
+    side = {"below": 0, "between": 0, "above": 0}
+    for trial in range(400):
+        amp = 10 ** rng.uniform(-9, 1)
+        rho = 1 + 0.02 * rng.standard_normal()
+        vx, vy = 0.05 * rng.standard_normal(2)
+        f = O.feq(lat.eps, rho, vx, vy) + amp * rng.standard_normal(9) * W9
+        f -= W9 * (f.sum() - rho)
+        nu = O.viscosity(lat, f, rho, vx, vy)
+        gstar = lat.gamma_scale * math.sqrt(O.shear_sq(lat, f, rho, vx, vy, 1 / (3 * nu + 0.5)))
+        expect = nu0 * min(max(gstar, g1), g2) ** (npow - 1)
+        assert nu == pytest.approx(expect, rel=1e-12), (gstar, nu, expect)
+        side["below" if gstar < g1 else "above" if gstar > g2 else "between"] += 1
+    assert side["below"] > 10 and side["between"] > 10, side
+    if g2 < 1e3:
+        assert side["above"] > 10, side

@@ -339,3 +339,73 @@ def test_cavity_centro_symmetry_is_restored_with_resolution():
     ratio_t = res[0][1] / res[1][1]
     assert res[1][0] < 2e-3 and res[1][1] < 3e-3, res
     assert ratio_u > 2.8 and ratio_t > 2.8, res
+
+
+def two_layer_brinkman(y, N, nu, eps, K1, K2, gx):
+    """Closed form of nu u'' - eps nu u / K(y) + eps gx = 0 between no-slip
+    walls at y = 0 and y = N, K = K1 below y = N/2 and K2 above: a cosh/sinh
+    pair plus the Darcy value gx K / nu in each layer, with u and u'
+    continuous at y = N/2."""
+    r1, r2, h = math.sqrt(eps / K1), math.sqrt(eps / K2), N / 2
+    d1, d2 = gx * K1 / nu, gx * K2 / nu
+    # u1 = -d1 cosh(r1 y) + B1 sinh(r1 y) + d1; u2 = -d2 cosh(r2 z) + B2 sinh(r2 z) + d2, z = N - y
+    A = np.array([[math.sinh(r1 * h), -math.sinh(r2 * h)],
+                  [r1 * math.cosh(r1 * h), r2 * math.cosh(r2 * h)]])
+    b = np.array([d1 * math.cosh(r1 * h) - d1 - d2 * math.cosh(r2 * h) + d2,
+                  r1 * d1 * math.sinh(r1 * h) + r2 * d2 * math.sinh(r2 * h)])
+    B1, B2 = np.linalg.solve(A, b)
+    z = N - y
+    u1 = -d1 * np.cosh(r1 * y) + B1 * np.sinh(r1 * y) + d1
+    u2 = -d2 * np.cosh(r2 * z) + B2 * np.sinh(r2 * z) + d2
+    return np.where(y < h, u1, u2)
+
+
+def test_per_cell_permeability_uniform_plane_is_brinkman():
+    """K(x) = 10^logDa(x) N^2 (Eq. 6, Da = K / L^2 with L = nx): a uniform
+    per-cell log10(Da) plane reproduces the Brinkman channel's cosh closed form
+    with K = Da nx^2 -- a dropped N^2, another base or a flipped sign of the
+    exponent each moves K by a factor of at least 4."""
+    errs = []
+    for N in (16, 32, 64):
+        nx, nu, eps, gx = 4, 0.1, 0.6, 1e-7
+        K = (N / 8) ** 2
+        lat = channel(N, nx=nx, nu0=nu, nu_min=nu, nu_max=nu, gx=gx, eps=eps, K=1e300)
+        assert lat.K_scale == nx * nx
+        logda = np.full((N, nx), math.log10(K / nx ** 2))
+        o = O.Oracle(lat, logda=logda)
+        o.step(int(3 * N * N / nu))
+        y = np.arange(N) + 0.5
+        r = math.sqrt(eps / K)
+        ua = gx * K / nu * (1 - np.cosh(r * (y - N / 2)) / math.cosh(r * N / 2))
+        ux = o.macros()["ux"]
+        assert np.abs(ux - ux[:, :1]).max() <= 1e-12 * ua.max()  # uniform along the channel
+        errs.append(np.abs(ux[:, 0] - ua).max() / ua.max())
+    assert errs[2] < 2e-3 and errs[0] / errs[1] > 3 and errs[1] / errs[2] > 3, errs
+    # the physical mapping uses the same scale: K_scale = nx^2 for the cavity
+    assert O.map_physics(O.physics(48, 40, Da=1e-2)).K_scale == 48.0 ** 2
+
+
+def test_per_cell_permeability_two_layers():
+    """A two-layer log10(Da) plane (Da = 1/64 below mid-channel, 1/16 above):
+    the profile converges to the piecewise cosh/sinh closed form, so each
+    node takes the permeability of its own cell."""
+    errs = []
+    for N in (16, 32, 64):
+        nx, nu, eps, gx = 2, 0.1, 0.6, 1e-7
+        K1, K2 = (N / 8) ** 2, (N / 4) ** 2
+        lat = channel(N, nx=nx, nu0=nu, nu_min=nu, nu_max=nu, gx=gx, eps=eps, K=1e300)
+        logda = np.empty((N, nx))
+        logda[: N // 2] = math.log10(K1 / nx ** 2)
+        logda[N // 2:] = math.log10(K2 / nx ** 2)
+        o = O.Oracle(lat, logda=logda)
+        o.step(int(4 * N * N / nu))
+        y = np.arange(N) + 0.5
+        ua = two_layer_brinkman(y, N, nu, eps, K1, K2, gx)
+        if N == 32:
+            # the layers matter: either uniform permeability is far off
+            for K in (K1, K2):
+                r = math.sqrt(eps / K)
+                uu = gx * K / nu * (1 - np.cosh(r * (y - N / 2)) / math.cosh(r * N / 2))
+                assert np.abs(uu - ua).max() / ua.max() > 0.1
+        errs.append(np.abs(o.macros()["ux"][:, 0] - ua).max() / ua.max())
+    assert errs[2] < 3e-3 and errs[0] / errs[1] > 3 and errs[1] / errs[2] > 3, errs
