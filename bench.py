@@ -9,16 +9,25 @@ run-to-steady loop.  W untimed warm-up steps, then K timed steps between two
 synchronisations.
 
 Metric: MLUPS (million node updates per second, flow + thermal).  Also
-reported: the roofline of the dominant kernel -- the two-step kernel, which
-advances every node by two steps per launch -- from HIP-event-timed launches
-against the 8 TB/s HBM peak, with 112 algorithmic bytes per node update (9 +
-5 FP32 populations read once and written once per step) times the 2 N^2
-updates of a launch; the kernel keeps the intermediate step on chip, so it
-moves about half of those bytes (see `traffic`).  Also the measured ceiling
-of a plain streaming copy, and the FP64 CPU oracle timed on a bounded sample
-of the same workload on this host.
+reported, for the dominant kernel (the two-step kernel, which advances every
+node by two steps per launch, at 4096^2 FP32):
+  * roofline.achieved / frac: the kernel's algorithmic bytes per launch --
+    one read and one write of the whole state, 112 B per node (9 + 5 FP32
+    populations), for either step kernel -- over the HIP-event-timed launch,
+    against the 8 TB/s HBM peak;
+  * alg_equiv_GBps / alg_equiv_frac: the method's 112 B per node update times
+    the 2 N^2 updates of a launch over the same time (the single-pass
+    roofline of the method, which the two-step kernel can pass);
+  * traffic / hbm_GBps / hbm_frac / copy_frac: the HBM bytes the kernel
+    really moves per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, committed
+    with a hash of the kernel code) over the launch time, against the peak
+    and against the measured streaming-copy ceiling;
+and the other FP32 rounding mode, the adjoint/forward cost of the gradient
+workload, a capped comparison of the 27-case sweep with sequential runs, and
+the FP64 CPU oracle timed on a bounded sample of the same workload on this
+host (all cores and one core).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-extras]
 """
 import argparse
 import hashlib
@@ -37,6 +46,7 @@ PHYS = dict(n=0.8, Da=1e-2, Ra=1e5, Pr=10.0, eps=0.6)
 BYTES_PER_NODE = 112  # 14 FP32 populations, each read once and written once per step
 HBM_PEAK_GBS = 8000.0
 CHECK_EVERY = 1000
+DEFAULT_ROUNDING = "nearest"  # the library's default for FP32 (pm_params_default)
 CSRC = os.path.join(ROOT, "paper_2011_15073_amd", "csrc")
 # The step kernels the benchmark can time (--step-kernel; the default "auto"
 # takes the two-step kernel at 4096^2), each with its committed counter
@@ -120,25 +130,56 @@ def read_traffic(kind="pair"):
         return None
 
 
-def cpu_baseline(budget_s=15.0):
-    """The FP64 oracle on the same 4096^2 workload: one warm-up step, then as
-    many steps as fit in about budget_s seconds (at least one)."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _oracle_sample(budget_s):
+    """Oracle MLUPS on the 4096^2 workload: one warm-up step, then as many
+    steps as fit in about budget_s seconds (at least one)."""
     import oracle as O
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
     orc = O.Oracle.from_physics(O.physics(N, **PHYS))
     t0 = time.perf_counter()
     orc.step(1)
-    t1 = time.perf_counter()
-    per = t1 - t0
+    per = time.perf_counter() - t0
     k = max(1, min(50, int(budget_s / max(per, 1e-3))))
     t0 = time.perf_counter()
     orc.step(k)
     dt = time.perf_counter() - t0
-    del orc
-    return {"value": round(N * N * k / dt / 1e6, 3), "unit": "MLUPS", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{k} steps of the 4096x4096 workload after 1 warm-up step, FP64, "
-                      f"{dt:.1f} s"}
+    return N * N * k / dt / 1e6, k, dt
+
+
+def cpu_baseline(budget_s=15.0, one_core=True):
+    """The FP64 oracle on the same 4096^2 workload, on all the host's cores
+    (OpenMP over rows), and on one core in a child process (one step, which
+    takes about 20-30 s there)."""
+    import subprocess
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+    mlups, k, dt = _oracle_sample(budget_s)
+    out = {"value": round(mlups, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+           "cpu_model": cpu_model(),
+           "sample": f"{k} steps of the 4096x4096 workload after 1 warm-up step, FP64, {dt:.1f} s, "
+                     f"{threads} OpenMP threads"}
+    if one_core:
+        env = dict(os.environ, OMP_NUM_THREADS="1")
+        code = ("import sys, json; sys.path.insert(0, %r); import bench; "
+                "m, k, dt = bench._oracle_sample(0.0); print(json.dumps([m, k, dt]))" % ROOT)
+        try:
+            r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                               timeout=300, check=True)
+            m1, k1, dt1 = json.loads(r.stdout.strip().splitlines()[-1])
+            out["value_1core"] = round(m1, 4)
+            out["sample_1core"] = f"{k1} step(s) of the same workload after 1 warm-up step, 1 thread, {dt1:.1f} s"
+        except (subprocess.SubprocessError, ValueError, IndexError) as e:
+            out["value_1core"] = None
+            out["sample_1core"] = f"not measured: {type(e).__name__}"
+    return out
 
 
 def sweep_main(args):
@@ -340,8 +381,12 @@ def main():
     ap.add_argument("--dtype", default="fp32", choices=["fp32", "fp64"],
                     help="storage and arithmetic of the timed cavity (fp64: the single-step kernel, 224 B per "
                          "node update)")
-    ap.add_argument("--rounding", default="nearest", choices=["nearest", "stochastic"],
-                    help="rounding of the FP32 population updates (PM_ROUND_*)")
+    ap.add_argument("--rounding", default=None, choices=["nearest", "stochastic"],
+                    help="rounding of the FP32 population updates (PM_ROUND_*; default: the library's)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the other rounding mode, the adjoint cost and the capped sweep")
+    ap.add_argument("--sweep-extra-cap", type=int, default=10000,
+                    help="step cap of the capped 27-case sweep comparison in the default run")
     ap.add_argument("--roofline-steps", type=int, default=400)
     ap.add_argument("--side", type=int, default=N,
                     help="grid side of the timed cavity (default 4096, the benchmark workload; other sides "
@@ -386,83 +431,28 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     S, dt = args.side, args.dtype
-    # the step kernel the library will run: only the two-step kernel (FP32)
-    # needs a second population region in the workspace
-    pair = (P.workspace_bytes(P.make_params(S, dtype=dt, step_kernel=args.step_kernel, **PHYS)) >
-            P.workspace_bytes(P.make_params(S, dtype=dt, step_kernel="single", **PHYS)))
-    kind = ("pair" if pair else "single") + ("_fp64" if dt == "fp64" else "")
-    if args.rounding == "stochastic" and kind + "_sr" in KERNELS:
-        kind += "_sr"
-    K = KERNELS[kind]
+    rounding = args.rounding or ("stochastic" if dt == "fp32" and DEFAULT_ROUNDING == "stochastic" else "nearest")
+    kind, K = kernel_kind(P, S, dt, args.step_kernel, rounding)
     spl = K["steps_per_launch"]
     bpn = BYTES_PER_NODE * (2 if dt == "fp64" else 1)
     log(f"bench: {S}x{S} {dt} {PHYS}, warmup {args.warmup}, steps {args.steps}, step kernel {args.step_kernel} "
-        f"({K['name'].split()[0]}), rounding {args.rounding}")
-    cav = P.Cavity(S, dtype=dt, device="cuda:0", step_kernel=args.step_kernel, rounding=args.rounding,
-                   **PHYS)
-    stream = cav.stream
-
-    # warm-up (also builds the step graphs)
-    cav.step(args.warmup)
-    cav.nu()
-    torch.cuda.synchronize()
-    log("bench: warm-up done")
-
-    # timed region: K steps with the on-device reductions every CHECK_EVERY steps
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    left = args.steps
-    nus = []
-    while left > 0:
-        k = min(CHECK_EVERY, left)
-        cav.step(k)
-        left -= k
-        if k == CHECK_EVERY:
-            nus.append(cav.nu())
-            cav.residual()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ms_per_step = elapsed * 1e3 / args.steps
-    mlups = S * S * args.steps / elapsed / 1e6
-    log(f"bench: {mlups:.1f} MLUPS, {ms_per_step:.4f} ms/step, Nu {nus[-1] if nus else cav.nu():.6f}")
-
-    # roofline of the step kernel: back-to-back launches (for the two-step
-    # kernel rs steps from an even step count: rs / 2 launches) bracketed by
-    # HIP events on the context's stream
-    rs = args.roofline_steps - args.roofline_steps % 4
-    with torch.cuda.stream(stream):
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        cav.step(rs)
-        e1.record(stream)
-    e1.synchronize()
-    per_step_s = e0.elapsed_time(e1) / 1e3 / rs
-    launch_s = spl * per_step_s
-    achieved = bpn * S * S * spl / launch_s / 1e9
-    log(f"bench: {K['name'].split()[0]} {launch_s * 1e6:.1f} us/launch ({per_step_s * 1e6:.1f} us/step), "
-        f"{achieved:.0f} GB/s algorithmic")
-
-    # measured streaming-copy ceiling (read + write of 1 GiB)
-    nbytes = 1 << 30
-    src = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
-    dst = torch.empty_like(src)
-    for _ in range(3):
-        P.copy_probe(src, dst, stream)
-    with torch.cuda.stream(stream):
-        c0 = torch.cuda.Event(enable_timing=True)
-        c1 = torch.cuda.Event(enable_timing=True)
-        c0.record(stream)
-        for _ in range(10):
-            P.copy_probe(src, dst, stream)
-        c1.record(stream)
-    c1.synchronize()
-    copy_gbs = 2 * nbytes * 10 / (c0.elapsed_time(c1) / 1e3) / 1e9
-    del src, dst
+        f"({K['name'].split()[0]}), rounding {rounding}")
+    run = time_cavity(P, S, dt, rounding, args.step_kernel, args.warmup, args.steps, args.roofline_steps)
+    mlups, ms_per_step, launch_s = run["mlups"], run["ms_per_step"], run["per_step_s"] * spl
+    # algorithmic bytes of one launch of either step kernel: the launch reads
+    # the whole state once and writes it once (the two-step kernel keeps its
+    # intermediate step on chip), 112 B (FP32) / 224 B (FP64) per node
+    alg_launch = bpn * S * S
+    achieved = alg_launch / launch_s / 1e9
+    alg_equiv = bpn * S * S * spl / launch_s / 1e9  # the method's 112 B per node update
+    log(f"bench: {K['name'].split()[0]} {launch_s * 1e6:.1f} us/launch, {achieved:.0f} GB/s kernel-algorithmic, "
+        f"{alg_equiv:.0f} GB/s at 112 B per node update")
+    copy_gbs = copy_ceiling(P, dev)
     log(f"bench: copy ceiling {copy_gbs:.0f} GB/s")
 
-    # counters were taken at 4096^2, with nearest rounding unless the kernel entry is a stochastic one
-    traffic = read_traffic(kind) if S == N and (args.rounding == "nearest" or kind.endswith("_sr")) else None
+    # counters were taken at 4096^2 on the kernel code the hash names
+    traffic = read_traffic(kind) if S == N else None
+    hbm = traffic / launch_s / 1e9 if traffic else None
     result = {
         "metric": "MLUPS (flow+thermal)",
         "value": round(mlups, 1),
@@ -480,23 +470,180 @@ def main():
                                f"{dt.upper()} AA layout, n=0.8 Da=1e-2 Ra=1e5 Pr=10 eps=0.6, "
                                "Nu + residual on device every 1000 steps",
                    "nodes": S * S, "steps_timed": args.steps, "step_kernel": args.step_kernel,
-                   "rounding": args.rounding},
+                   "rounding": rounding},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
+                     "hbm_GBps": round(hbm, 1) if hbm else None,
+                     "hbm_frac": round(hbm / HBM_PEAK_GBS, 4) if hbm else None,
+                     "copy_frac": round(hbm / copy_gbs, 4) if hbm else None,
+                     "alg_equiv_GBps": round(alg_equiv, 1),
+                     "alg_equiv_frac": round(alg_equiv / HBM_PEAK_GBS, 4),
                      "kernel": K["name"],
                      "steps_per_launch": spl,
                      "us_per_launch": round(launch_s * 1e6, 2),
-                     "algorithmic_bytes_per_launch": bpn * S * S * spl,
+                     "algorithmic_bytes_per_launch": alg_launch,
                      "copy_ceiling_GBps": round(copy_gbs, 1)},
-        "nu_bar": nus[-1] if nus else None,
+        "nu_bar": run["nu"],
     }
+    del run
+    torch.cuda.empty_cache()
+    if dt == "fp32" and not args.no_extras:
+        other = "nearest" if rounding == "stochastic" else "stochastic"
+        kind_o, K_o = kernel_kind(P, S, dt, args.step_kernel, other)
+        o = time_cavity(P, S, dt, other, args.step_kernel, args.warmup, args.steps, args.roofline_steps)
+        result["other_rounding"] = {"rounding": other, "mlups": round(o["mlups"], 1),
+                                    "ms_per_step": round(o["ms_per_step"], 5),
+                                    "us_per_launch": round(o["per_step_s"] * K_o["steps_per_launch"] * 1e6, 2),
+                                    "kernel": K_o["name"]}
+        log(f"bench: {other} rounding: {o['mlups']:.1f} MLUPS")
+        del o
+        torch.cuda.empty_cache()
+    if not args.no_extras:
+        result["adjoint"] = adjoint_cost(P, 5000, args.adjoint_shear_floor)
+        result["sweep_capped"] = sweep_capped(P, args.sweep_extra_cap)
     if not args.no_cpu_baseline and S == N:
-        del cav
         torch.cuda.empty_cache()
         log("bench: timing the CPU oracle on a bounded sample ...")
         result["cpu_baseline"] = cpu_baseline()
     print(json.dumps(result), flush=True)
+
+
+def kernel_kind(P, S, dt, step_kernel, rounding):
+    """The step kernel the library will run (only the two-step kernel needs a
+    second population region) and its entry in KERNELS."""
+    pair = (P.workspace_bytes(P.make_params(S, dtype=dt, step_kernel=step_kernel, **PHYS)) >
+            P.workspace_bytes(P.make_params(S, dtype=dt, step_kernel="single", **PHYS)))
+    kind = ("pair" if pair else "single") + ("_fp64" if dt == "fp64" else "")
+    if rounding == "stochastic" and kind + "_sr" in KERNELS:
+        kind += "_sr"
+    return kind, KERNELS[kind]
+
+
+def time_cavity(P, S, dt, rounding, step_kernel, warmup, steps, roofline_steps):
+    """The timed run: warm-up, then `steps` steps with the on-device Nu and
+    residual every CHECK_EVERY steps between two synchronisations; then the
+    step time from HIP events on the context's stream around
+    roofline_steps steps (a multiple of 4: whole two-step pairs)."""
+    import torch
+    cav = P.Cavity(S, dtype=dt, device="cuda:0", step_kernel=step_kernel, rounding=rounding, **PHYS)
+    stream = cav.stream
+    cav.step(warmup)  # also builds the step graphs
+    cav.nu()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    left, nus = steps, []
+    while left > 0:
+        k = min(CHECK_EVERY, left)
+        cav.step(k)
+        left -= k
+        if k == CHECK_EVERY:
+            nus.append(cav.nu())
+            cav.residual()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    nu = nus[-1] if nus else cav.nu()
+    log(f"bench: {rounding}: {S * S * steps / elapsed / 1e6:.1f} MLUPS, {elapsed * 1e3 / steps:.4f} ms/step, "
+        f"Nu {nu:.6f}")
+    rs = roofline_steps - roofline_steps % 4
+    with torch.cuda.stream(stream):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        cav.step(rs)
+        e1.record(stream)
+    e1.synchronize()
+    out = {"mlups": S * S * steps / elapsed / 1e6, "ms_per_step": elapsed * 1e3 / steps, "nu": nu,
+           "per_step_s": e0.elapsed_time(e1) / 1e3 / rs}
+    del cav
+    return out
+
+
+def copy_ceiling(P, dev):
+    """Streaming copy of 1 GiB (read + write) with the library's copy kernel."""
+    import torch
+    nbytes = 1 << 30
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    stream = torch.cuda.current_stream(dev)
+    for _ in range(3):
+        P.copy_probe(src, dst, stream)
+    c0 = torch.cuda.Event(enable_timing=True)
+    c1 = torch.cuda.Event(enable_timing=True)
+    c0.record(stream)
+    for _ in range(10):
+        P.copy_probe(src, dst, stream)
+    c1.record(stream)
+    c1.synchronize()
+    return 2 * nbytes * 10 / (c0.elapsed_time(c1) / 1e3) / 1e9
+
+
+def adjoint_cost(P, T, shear_floor):
+    """The gradient workload (256^2, FP32 forward state, n = 0.7, Ra = 1e4,
+    per-cell log10 Da seed 0, J = Nu_bar after T steps): backward (segment
+    replays + adjoint steps) over forward (with checkpoints), wall clock,
+    second of two repetitions."""
+    import torch
+    from paper_2011_15073_amd import inputs
+    ld = torch.from_numpy(inputs.logda_field(256, seed=0))
+    for rep in range(2):
+        cav = P.Cavity(256, dtype="fp32", logda=ld, n=0.7, Ra=1e4, Pr=10.0, eps=0.6)
+        adj = P.Adjoint(cav, T, shear_floor=shear_floor)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        J = adj.forward()
+        t1 = time.perf_counter()
+        adj.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        adj.close()
+        del adj, cav
+    log(f"bench: adjoint {T} steps: forward {t1 - t0:.4f} s, backward {t2 - t1:.4f} s")
+    return {"adjoint_over_forward": round((t2 - t1) / (t1 - t0), 3), "forward_s": round(t1 - t0, 4),
+            "backward_s": round(t2 - t1, 4), "T": T, "J": J, "shear_floor": shear_floor,
+            "workload": "256x256, n=0.7, Ra=1e4, Pr=10, eps=0.6, log10 Da ~ U[-3,-1] (seed 0), FP32 forward / "
+                        "FP64 adjoint, checkpoints every ceil(sqrt(T)) steps"}
+
+
+def sweep_capped(P, cap, dtype="fp64"):
+    """The 27-case sweep with every case capped at `cap` steps (tol 1e-8,
+    checks every 1000 steps; few cases stop before the cap): one batched
+    sweep with the tuned schedule against the cases run one after another,
+    wall clock, and whether every case ends bitwise equal."""
+    import torch
+    from paper_2011_15073_amd import inputs
+    cs = inputs.sweep_cases(0)
+    cases = [dict(nx=c["N"], n=c["n"], Da=c["Da"], Ra=c["Ra"], Pr=10.0, eps=0.6, dtype=dtype) for c in cs]
+    sched, _ = P.tune(cases)
+    sw = P.Sweep(cases, **sched)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    steps, _ = sw.run(tol=1e-8, check_every=1000, max_steps=cap)
+    torch.cuda.synchronize()
+    t_b = time.perf_counter() - t0
+    t_s, same = 0.0, 0
+    tdt = torch.float64 if dtype == "fp64" else torch.float32
+    for i, kw in enumerate(cases):
+        kw = dict(kw)
+        cav = P.Cavity(kw.pop("nx"), **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r, st = cav.run_to_steady(tol=1e-8, check_every=1000, max_steps=cap)
+        torch.cuda.synchronize()
+        t_s += time.perf_counter() - t0
+        fa, ga = cav.populations(tdt)
+        fb, gb = sw.case(i).populations(tdt)
+        same += int(st == steps[i] and torch.equal(fa, fb) and torch.equal(ga, gb))
+        del cav
+    sw.close()
+    log(f"bench: sweep capped at {cap}: batched {t_b:.2f} s, sequential {t_s:.2f} s, {same}/27 bitwise")
+    nupd = sum(st * c["N"] ** 2 for st, c in zip(steps, cs))
+    return {"speedup_vs_sequential": round(t_s / t_b, 3), "batched_s": round(t_b, 3),
+            "sequential_s": round(t_s, 3), "batched_MLUPS": round(nupd / t_b / 1e6, 1),
+            "cases_bitwise_equal": f"{same}/{len(cases)}", "cap": cap, "dtype": dtype,
+            "schedule": {"order": sched["order"], "tile": list(sched["tile"])},
+            "workload": "27 cases n x Da x Ra, eps=0.6, Pr=10, sides from {128,...,512} (seed 0), "
+                        f"tol 1e-8 every 1000 steps, capped at {cap} steps"}
 
 
 if __name__ == "__main__":

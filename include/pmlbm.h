@@ -106,9 +106,10 @@ typedef struct {
                              step, and the cavity's slowly decaying modes turn that fixed pattern
                              into a bias (about 5e-4 of the fields at the 256^2 power-law steady
                              state).  Stochastic rounding adds each node's update to its stored
-                             populations with a +-1/2-ulp dither from a hash of the node and its
-                             inputs: deterministic, the same in every kernel, unbiased, and about
-                             20% more time per step at 4096^2.  PM_EINVAL with FP64. */
+                             populations with a uniform dither of width 2 ulp of the stored value,
+                             one 24-bit uniform per node update from a hash of the node and its
+                             inputs: deterministic, the same in every kernel, unbiased.
+                             PM_EINVAL with FP64. */
 } pm_params;
 
 /* Lattice values derived from pm_params (read-only description). */
@@ -132,11 +133,17 @@ int pm_lattice_of(const pm_params* p, pm_lattice* out);
 /* Device workspace size (bytes) that pm_init needs for p. */
 int pm_workspace_bytes(const pm_params* p, size_t* bytes);
 
-/* Create a context: validates p, carves the caller's device workspace
- * dev_ws (at least pm_workspace_bytes, 256-byte aligned, on the current
- * device), and enqueues the rest-state initialisation (rho = 1, u = 0,
- * theta = T_init) on hip_stream (a hipStream_t; NULL = default stream).
- * The workspace must stay allocated until pm_destroy. */
+/* Create a context for the cavity problem of the paper's "Mathematical
+ * Formulations" section: side L = nx nodes, groups n, Da, Ra, Pr of Eq. (6)
+ * plus eps, mapped to lattice values as described at the top of this file.
+ * Validates p, carves the caller's device workspace dev_ws (at least
+ * pm_workspace_bytes, 256-byte aligned, on the current device), and enqueues
+ * the rest-state initialisation (rho = 1, u = 0, theta = T_init, the
+ * equilibrium populations) on hip_stream (a hipStream_t; NULL = default
+ * stream).  The workspace must stay allocated until pm_destroy.  Errors:
+ * PM_EINVAL for invalid parameters or a misaligned workspace, PM_ESTATE for
+ * a workspace that is too small, PM_EDEVICE for a HIP failure; *out is then
+ * NULL. */
 int pm_init(const pm_params* p, void* dev_ws, size_t ws_bytes, void* hip_stream,
             pm_ctx** out);
 
@@ -148,8 +155,12 @@ void pm_destroy(pm_ctx* ctx);
  * has_logda = 1.  Async. */
 int pm_set_logda(pm_ctx* ctx, const void* dev_plane, int dtype);
 
-/* Advance k >= 0 time steps (one step = stream + collide of every node for
- * both populations).  Async. */
+/* Advance k >= 0 time steps.  One step is the D2Q9 MRT update of Eq. (12)
+ * (collision in moment space with the relaxation rates of Eq. (13), the
+ * local viscosity of Eqs. (21)-(23), buoyancy and porous drag as the forcing
+ * term, then streaming with halfway bounce-back walls) and the D2Q5 MRT
+ * update of Eq. (18) (hot/cold anti-bounce-back walls, adiabatic
+ * bounce-back walls), for every node.  Async; PM_EINVAL for k < 0. */
 int pm_step(pm_ctx* ctx, int64_t k);
 
 /* Steps done since pm_init / the last pm_set_populations or pm_load_state. */
@@ -160,9 +171,11 @@ int pm_steps_done(const pm_ctx* ctx, int64_t* steps);
 int pm_nu(pm_ctx* ctx, double* nu_out);
 
 /* Steady-state residual: r = max over nodes of |theta - theta_snapshot|
- * (FP64), then snapshot := theta.  The snapshot is taken at pm_init.
- * Synchronises.  PM_EDIVERGED (with *r_out = +inf) if a NaN/Inf is met. */
-int pm_residual(pm_ctx* ctx, double* r_out);
+ * (FP64), then snapshot := theta.  The snapshot is taken at pm_init (and
+ * restored by pm_load_state).  *at_step (may be NULL) = the step count at
+ * which r was taken, i.e. pm_steps_done.  Synchronises.  PM_EDIVERGED (with
+ * *r_out = +inf) if a NaN/Inf is met. */
+int pm_residual(pm_ctx* ctx, double* r_out, int64_t* at_step);
 
 /* Run in chunks of check_every steps, calling pm_residual after each, until
  * r < tol or max_steps steps were taken by this call.  *steps_out = steps
@@ -170,9 +183,11 @@ int pm_residual(pm_ctx* ctx, double* r_out);
 int pm_run_to_steady(pm_ctx* ctx, double tol, int64_t check_every, int64_t max_steps,
                      int64_t* steps_out, double* r_out);
 
-/* Nondimensional fields of the current state into caller device buffers
- * [ny][nx] of dtype PM_FP32 / PM_FP64: U = u/U_lb, V = v/U_lb (u is the
- * porous velocity of the update), theta.  Any pointer may be NULL.  Async. */
+/* Nondimensional fields of Eq. (6) for the current state into caller device
+ * buffers [ny][nx] of dtype PM_FP32 / PM_FP64: U = u/U_lb, V = v/U_lb (u the
+ * porous velocity of the update, from rho and j of Eqs. (16)-(17)) and
+ * theta = T of Eq. (20) (the walls are at theta = 1 and 0).  Any pointer may
+ * be NULL.  Async.  PM_EINVAL for a bad dtype. */
 int pm_fields(pm_ctx* ctx, void* U, void* V, void* theta, int dtype);
 
 /* Stream function of the current state [ny][nx] (the streamline plots of
@@ -196,9 +211,16 @@ int pm_get_populations(pm_ctx* ctx, void* f, void* g, int dtype);
  * resets the step count to 0.  Async. */
 int pm_set_populations(pm_ctx* ctx, const void* f, const void* g, int dtype);
 
-/* Raw state checkpoint: pm_state_bytes gives the size; save/load copy the
- * population region plus the step count between the workspace and a caller
- * device buffer.  Loading restores the step count.  Async. */
+/* Raw state checkpoint: pm_state_bytes gives the size; save/load copy, between
+ * the workspace and a caller device buffer, a header (grid and dtype tag, the
+ * step count, a hash of the physics: the lattice values of pm_lattice, n,
+ * the body force, has_logda, the periodic axes and the rounding mode), the
+ * population region and the residual snapshot, so that a resumed
+ * pm_run_to_steady stops where the uninterrupted run stops.  The log-Da
+ * plane is not saved (set it again after loading into a new context).
+ * pm_load_state checks the header synchronously: PM_ESTATE if the buffer is
+ * too small, or was saved for another grid, dtype or physics (nothing is
+ * loaded then).  Loading restores the step count.  The copies are async. */
 int pm_state_bytes(const pm_ctx* ctx, size_t* bytes);
 int pm_save_state(pm_ctx* ctx, void* dev_dst, size_t bytes);
 int pm_load_state(pm_ctx* ctx, const void* dev_src, size_t bytes);
@@ -247,8 +269,11 @@ int pm_sweep_set_order(pm_sweep* s, int order);
  * the same for every shape; used by the autotuner.  Synchronises the stream.
  * PM_EINVAL for any other shape. */
 int pm_sweep_set_tile(pm_sweep* s, int tile_w, int tile_h);
-/* Run every live case until it stops (see above).  steps_out[i], r_out[i]
- * (arrays of ncases, may be NULL): steps taken and last residual of case i.
+/* Run every live case until it stops (see above).  max_steps counts every
+ * step a case has taken since pm_sweep_create (all run, advance and step
+ * calls together); the chunk that reaches it is shortened, as
+ * pm_run_to_steady shortens its last one.  steps_out[i], r_out[i] (arrays
+ * of ncases, may be NULL): steps taken and last residual of case i.
  * Returns PM_EDIVERGED if any case stopped on NaN/Inf. */
 int pm_sweep_run(pm_sweep* s, double tol, int64_t check_every, int64_t max_steps, int64_t* steps_out,
                  double* r_out);
@@ -322,6 +347,7 @@ const char* pm_adjoint_last_error(const pm_adjoint* a);
 size_t pm_adjoint_vjp_scratch_bytes(const pm_ctx* ctx);
 int pm_adjoint_vjp(pm_ctx* ctx, const void* lam_next, void* lam, void* grad_logda, void* dev_scratch,
                    size_t scratch_bytes, double* grad_scalars);
+
 
 const char* pm_strerror(int code);
 const char* pm_last_error(const pm_ctx* ctx);

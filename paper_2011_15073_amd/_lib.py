@@ -85,7 +85,7 @@ def _load():
         "pm_step": ([vp, i64], i32),
         "pm_steps_done": ([vp, P(i64)], i32),
         "pm_nu": ([vp, P(dbl)], i32),
-        "pm_residual": ([vp, P(dbl)], i32),
+        "pm_residual": ([vp, P(dbl), P(i64)], i32),
         "pm_run_to_steady": ([vp, dbl, i64, i64, P(i64), P(dbl)], i32),
         "pm_fields": ([vp, vp, vp, vp, i32], i32),
         "pm_viscosity": ([vp, vp, i32], i32),

@@ -89,10 +89,12 @@ class Cavity:
         self._check(lib.pm_nu(self._h, C.byref(v)))
         return v.value
 
-    def residual(self) -> float:
-        v = C.c_double()
-        self._check(lib.pm_residual(self._h, C.byref(v)))
-        return v.value
+    def residual(self, with_step=False):
+        """max |theta - theta_snapshot| since the last call (then snapshot :=
+        theta); with_step: also the step count at which it was taken."""
+        v, at = C.c_double(), C.c_int64()
+        self._check(lib.pm_residual(self._h, C.byref(v), C.byref(at)))
+        return (v.value, at.value) if with_step else v.value
 
     def run_to_steady(self, tol=1e-8, check_every=1000, max_steps=10_000_000):
         steps, r = C.c_int64(), C.c_double()

@@ -360,6 +360,35 @@ int sync_read(pm_ctx* c, double* host, const double* dev, int n) {
 
 int dtype_ok(int d) { return d == PM_FP32 || d == PM_FP64; }
 
+// Checkpoint header: [tag of grid and dtype, step count, physics hash], then
+// the population region and the residual snapshot plane.
+uint64_t state_tag(const pm_ctx* c) {
+  return STATE_TAG ^ ((uint64_t)c->p.nx << 32) ^ (uint64_t)c->p.ny ^ ((uint64_t)c->p.dtype << 60);
+}
+
+// FNV-1a (64-bit) over the lattice values the update runs with (so that the
+// same physics given with default or explicit rates hashes the same) and the
+// switches that change results.  The log-Da plane's contents are not hashed.
+uint64_t physics_hash(const pm_ctx* c) {
+  uint64_t h = 0xcbf29ce484222325ull;
+  auto eat = [&](const void* v, size_t n) {
+    const unsigned char* b = (const unsigned char*)v;
+    for (size_t i = 0; i < n; ++i) {
+      h ^= b[i];
+      h *= 0x100000001b3ull;
+    }
+  };
+  const pm_lattice& L = c->L;
+  const double d[] = {c->p.n, L.U_lb, L.nu0, L.nu_min, L.nu_max, L.gamma_scale, L.eps, L.K, L.Feps, L.gbeta,
+                      L.alpha, L.s_e, L.s_eps, L.s_q, L.sT_e, L.sT_nu, c->p.gx, c->p.gy};
+  const int32_t k[] = {c->p.has_logda, c->p.periodic_x, c->p.periodic_y, c->p.rounding};
+  eat(d, sizeof d);
+  eat(k, sizeof k);
+  return h;
+}
+
+size_t snap_bytes(const pm_ctx* c) { return c->lay.plane * c->lay.elem; }
+
 int init_ctx(const pm_params* p, void* dev_ws, size_t ws_bytes, void* hip_stream, bool pair, pm_ctx** out);
 
 }  // namespace
@@ -556,8 +585,9 @@ int pm_nu(pm_ctx* c, double* nu_out) {
   return PM_OK;
 }
 
-int pm_residual(pm_ctx* c, double* r_out) {
+int pm_residual(pm_ctx* c, double* r_out, int64_t* at_step) {
   if (!c || !r_out) return PM_EINVAL;
+  if (at_step) *at_step = c->steps;
   const int parity = (int)(c->steps & 1);
   double* dev = c->red + pm::RED_BLOCKS;
   hipError_t e = dispatch(c, [&](auto& kp) {
@@ -585,7 +615,7 @@ int pm_run_to_steady(pm_ctx* c, double tol, int64_t check_every, int64_t max_ste
     rc = pm_step(c, k);
     if (rc) break;
     done += k;
-    rc = pm_residual(c, &r);
+    rc = pm_residual(c, &r, nullptr);
     if (rc) break;
     if (r < tol) break;
   }
@@ -653,7 +683,7 @@ int pm_set_populations(pm_ctx* c, const void* f, const void* g, int dtype) {
 
 int pm_state_bytes(const pm_ctx* c, size_t* bytes) {
   if (!c || !bytes) return PM_EINVAL;
-  *bytes = HEADER_BYTES + c->lay.pop_bytes;
+  *bytes = HEADER_BYTES + c->lay.pop_bytes + snap_bytes(c);
   return PM_OK;
 }
 
@@ -662,11 +692,13 @@ int pm_save_state(pm_ctx* c, void* dst, size_t bytes) {
   size_t need;
   pm_state_bytes(c, &need);
   if (bytes < need) return ctx_fail(c, PM_ESTATE, "pm_save_state: buffer of %zu bytes < %zu", bytes, need);
-  const uint64_t tag = STATE_TAG ^ ((uint64_t)c->p.nx << 32) ^ (uint64_t)c->p.ny ^ ((uint64_t)c->p.dtype << 60);
-  hipError_t e = pm::launch_write_header(dst, c->steps, tag, c->stream);
+  hipError_t e = pm::launch_write_header(dst, c->steps, state_tag(c), physics_hash(c), c->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync((char*)dst + HEADER_BYTES, (char*)c->ws + c->lay.off_f, c->lay.pop_bytes,
                        hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync((char*)dst + HEADER_BYTES + c->lay.pop_bytes, (char*)c->ws + c->lay.off_snap,
+                       snap_bytes(c), hipMemcpyDeviceToDevice, c->stream);
   return check_hip(c, e, "pm_save_state");
 }
 
@@ -675,15 +707,21 @@ int pm_load_state(pm_ctx* c, const void* src, size_t bytes) {
   size_t need;
   pm_state_bytes(c, &need);
   if (bytes < need) return ctx_fail(c, PM_ESTATE, "pm_load_state: buffer of %zu bytes < %zu", bytes, need);
-  int64_t hdr[2];
+  int64_t hdr[3];
   hipError_t e = hipMemcpyAsync(hdr, src, sizeof hdr, hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return check_hip(c, e, "pm_load_state header");
-  const uint64_t tag = STATE_TAG ^ ((uint64_t)c->p.nx << 32) ^ (uint64_t)c->p.ny ^ ((uint64_t)c->p.dtype << 60);
-  if ((uint64_t)hdr[0] != tag || hdr[1] < 0)
+  if ((uint64_t)hdr[0] != state_tag(c) || hdr[1] < 0)
     return ctx_fail(c, PM_ESTATE, "pm_load_state: checkpoint does not match this grid/dtype");
+  if ((uint64_t)hdr[2] != physics_hash(c))
+    return ctx_fail(c, PM_ESTATE,
+                    "pm_load_state: checkpoint was saved with other physics (n, Da, Ra, Pr, eps, Mach, viscosity "
+                    "bounds, rates, body force, log-Da plane use, periodic axes or rounding differ)");
   e = hipMemcpyAsync((char*)c->ws + c->lay.off_f, (const char*)src + HEADER_BYTES, c->lay.pop_bytes,
                      hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync((char*)c->ws + c->lay.off_snap, (const char*)src + HEADER_BYTES + c->lay.pop_bytes,
+                       snap_bytes(c), hipMemcpyDeviceToDevice, c->stream);
   if (e != hipSuccess) return check_hip(c, e, "pm_load_state");
   c->steps = hdr[1];
   return PM_OK;
@@ -1044,12 +1082,28 @@ int pm_sweep_advance(pm_sweep* s, double tol, int64_t check_every, int64_t max_s
     live = 0;
     for (int i = 0; i < s->ncases; ++i) live += s->h_live[i];
     if (!live || chunk >= max_chunks) break;
+    // every live case has taken gsteps steps: stop them all at the cap, and
+    // shorten the chunk that reaches it, as pm_run_to_steady shortens its last
+    if (s->gsteps >= max_steps) {
+      std::fill(s->h_live.begin(), s->h_live.end(), 0);
+      e = hipMemcpyAsync(s->d_live, s->h_live.data(), s->ncases * sizeof(int), hipMemcpyHostToDevice, s->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+      if (e != hipSuccess) return sweep_fail(s, PM_EDEVICE, "pm_sweep_advance: %s", hipGetErrorString(e));
+      live = 0;
+      break;
+    }
+    const int64_t k = std::min(check_every, max_steps - s->gsteps);
     const int parity = (int)(s->gsteps & 1);
-    int rc = sweep_graph(s, parity, check_every, tol, max_steps);
-    if (rc) return rc;
-    e = hipGraphLaunch(s->graph[parity], s->stream);
-    if (e != hipSuccess) return sweep_fail(s, PM_EDEVICE, "hipGraphLaunch: %s", hipGetErrorString(e));
-    s->gsteps += check_every;
+    if (k == check_every) {
+      int rc = sweep_graph(s, parity, check_every, tol, max_steps);
+      if (rc) return rc;
+      e = hipGraphLaunch(s->graph[parity], s->stream);
+      if (e != hipSuccess) return sweep_fail(s, PM_EDEVICE, "hipGraphLaunch: %s", hipGetErrorString(e));
+    } else {
+      e = sweep_enqueue_chunk(s, s->stream, k, parity, tol, max_steps);
+      if (e != hipSuccess) return sweep_fail(s, PM_EDEVICE, "pm_sweep_advance: %s", hipGetErrorString(e));
+    }
+    s->gsteps += k;
     e = hipMemcpyAsync(s->h_live.data(), s->d_live, s->ncases * sizeof(int), hipMemcpyDeviceToHost, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) return sweep_fail(s, PM_EDEVICE, "pm_sweep_advance: %s", hipGetErrorString(e));

@@ -401,19 +401,21 @@ __device__ __forceinline__ void node_macros(const KParams<T>& p, int k, const T 
   uy = vy * iden;
 }
 
-// The full local update: Steps 2-9 on shifted populations, in place.
 // ---- stochastic rounding of the FP32 population updates (PM_ROUND_STOCHASTIC) ----
 // With round-to-nearest, a state near a steady flow rounds the same way step
 // after step, and the slowly decaying modes of the cavity accumulate that
 // fixed rounding pattern into a bias far above one rounding.  The update is
-// therefore written as f* = f + df (df from the moment changes) and added with
-// a dither xi uniform in (-1/2, 1/2) ulp of the sum: rounding a + (b + xi) to
-// nearest rounds a + b up or down with probability given by its position
-// between the two neighbours (stochastic rounding, to within 1/512 ulp with
-// 8-bit uniforms).  The uniforms come from a 32-bit integer mixer
-// (xorshift-multiply rounds) of the node index and of the node's incoming
-// populations, so the result is deterministic and the same in every kernel
-// that updates the node.
+// therefore written as f* = a + b (a the stored population, b its change from
+// the moment changes) and added as a + (b + xi), xi uniform on
+// (-ulp(a), ulp(a)), then rounded to nearest.  A uniform dither whose width is
+// a whole number of grid spacings leaves rounding to nearest unbiased, and
+// 2 ulp(a) is one, two or four spacings at a + b (a + b one binade above a,
+// in a's binade, or one below).  One uniform per node update serves all 14
+// populations (each is still rounded without bias); it has 24 bits and comes
+// from one round of the "lowbias32" integer hash (Chris Wellons, hash
+// prospector, public domain) of the node index and three of the node's
+// incoming populations, so it is deterministic, changes from step to step as
+// the state does, and is the same in every kernel that updates the node.
 __device__ __forceinline__ unsigned mix32(unsigned x) {
   x ^= x >> 16;
   x *= 0x7feb352du;
@@ -423,14 +425,23 @@ __device__ __forceinline__ unsigned mix32(unsigned x) {
   return x;
 }
 
-// a + b rounded with the dither byte ub (0..255) of a uniform.
-__device__ __forceinline__ float dither_add(float a, float b, unsigned ub) {
-  const float s0 = a + b;
-  const float ulp = __uint_as_float(__float_as_uint(s0) & 0x7f800000u) * 0x1p-23f;  // 0 for 0 / subnormal
-  const float xi = (float)ub * (1.0f / 256.0f) + (0.5f / 256.0f - 0.5f);
-  return a + __builtin_fmaf(xi, ulp, b);
+// The node's dither scale: u 2^-22 with u uniform on (-1/2, 1/2), so that
+// us * 2^e(a) = u * 2 ulp(a).
+__device__ __forceinline__ float dither_scale(int k, float a0, float a1, float a2) {
+  const unsigned h = mix32((unsigned)k * 0x9e3779b1u ^ __float_as_uint(a0) ^
+                           __builtin_amdgcn_alignbit(__float_as_uint(a1), __float_as_uint(a1), 11) ^
+                           __builtin_amdgcn_alignbit(__float_as_uint(a2), __float_as_uint(a2), 22));
+  return __builtin_fmaf((float)(h >> 8), 0x1p-46f, (0x1p-25f - 0.5f) * 0x1p-22f);
 }
 
+// a + b rounded with the node's dither (2^e(a) is 0 for a zero or subnormal a:
+// no dither there).
+__device__ __forceinline__ float dither_add(float a, float b, float us) {
+  const float p2 = __uint_as_float(__float_as_uint(a) & 0x7f800000u);
+  return a + __builtin_fmaf(us, p2, b);
+}
+
+// The full local update: Steps 2-9 on shifted populations, in place.
 template <typename T, bool POW, bool LOGDA, bool SR = false>
 __device__ __forceinline__ void collide(const KParams<T>& p, int k, T df[9], T dg[5]) {
   T drho, rho, jx, jy, dT, Gx, Gy, nu, ux, uy, invK, invsK, m1, m7, m8;
@@ -473,13 +484,10 @@ __device__ __forceinline__ void collide(const KParams<T>& p, int k, T df[9], T d
   const T b58 = (a0 + T(2) * a1) + a2;
   const T x1 = a3 - T(2) * a4, y1 = a5 - T(2) * a6;
   const T x5 = a3 + a4, y5 = a5 + a6;
-  unsigned h[4] = {0u, 0u, 0u, 0u};  // 16 dither bytes (SR)
+  float us = 0.0f;  // the node's dither scale (SR)
   if constexpr (SR) {
     static_assert(sizeof(T) == 4, "stochastic rounding is for FP32 storage");
-    const unsigned seed = mix32((unsigned)k * 0x9e3779b1u ^ __float_as_uint(df[0]) ^
-                                __float_as_uint(dg[0]) * 0x85ebca77u ^ __float_as_uint(df[5]) * 0xc2b2ae3du);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) h[r] = mix32(seed + 0x632be5abu * (unsigned)(r + 1));
+    us = dither_scale(k, df[0], dg[0], df[5]);
     // the same back-transform applied to the moment changes ms - m (the
     // density is conserved), added to the incoming populations
     const T d1 = (ms1 - m1) * T(1.0 / 36.0), d2 = (ms2 - m2) * T(1.0 / 36.0);
@@ -489,15 +497,15 @@ __device__ __forceinline__ void collide(const KParams<T>& p, int k, T df[9], T d
     const T e14 = -d1 - T(2) * d2, e58 = T(2) * d1 + d2;
     const T u1 = d3 - T(2) * d4, v1 = d5 - T(2) * d6;
     const T u5 = d3 + d4, v5 = d5 + d6;
-    df[0] = dither_add(df[0], T(4) * (d2 - d1), h[0] & 0xffu);
-    df[1] = dither_add(df[1], (e14 + u1) + d7, (h[0] >> 8) & 0xffu);
-    df[2] = dither_add(df[2], (e14 + v1) - d7, (h[0] >> 16) & 0xffu);
-    df[3] = dither_add(df[3], (e14 - u1) + d7, h[0] >> 24);
-    df[4] = dither_add(df[4], (e14 - v1) - d7, h[1] & 0xffu);
-    df[5] = dither_add(df[5], (e58 + u5) + (v5 + d8), (h[1] >> 8) & 0xffu);
-    df[6] = dither_add(df[6], (e58 - u5) + (v5 - d8), (h[1] >> 16) & 0xffu);
-    df[7] = dither_add(df[7], (e58 - u5) - (v5 - d8), h[1] >> 24);
-    df[8] = dither_add(df[8], (e58 + u5) - (v5 + d8), h[2] & 0xffu);
+    df[0] = dither_add(df[0], T(4) * (d2 - d1), us);
+    df[1] = dither_add(df[1], (e14 + u1) + d7, us);
+    df[2] = dither_add(df[2], (e14 + v1) - d7, us);
+    df[3] = dither_add(df[3], (e14 - u1) + d7, us);
+    df[4] = dither_add(df[4], (e14 - v1) - d7, us);
+    df[5] = dither_add(df[5], (e58 + u5) + (v5 + d8), us);
+    df[6] = dither_add(df[6], (e58 - u5) + (v5 - d8), us);
+    df[7] = dither_add(df[7], (e58 - u5) - (v5 - d8), us);
+    df[8] = dither_add(df[8], (e58 + u5) - (v5 + d8), us);
   } else {
     df[0] = (a0 - T(4) * a1) + T(4) * a2;
     df[1] = (b14 + x1) + a7;
@@ -521,11 +529,11 @@ __device__ __forceinline__ void collide(const KParams<T>& p, int k, T df[9], T d
   if constexpr (SR) {
     const T e1 = (ns1 - n1) * T(0.5), e2 = (ns2 - n2) * T(0.5);
     const T e3 = (ns3 - n3) * T(0.05), e4 = (ns4 - n4) * T(0.25);  // T is conserved
-    dg[0] = dither_add(dg[0], T(-4) * e3, (h[2] >> 8) & 0xffu);
-    dg[1] = dither_add(dg[1], (e3 + e1) + e4, (h[2] >> 16) & 0xffu);
-    dg[2] = dither_add(dg[2], (e3 + e2) - e4, h[2] >> 24);
-    dg[3] = dither_add(dg[3], (e3 - e1) + e4, h[3] & 0xffu);
-    dg[4] = dither_add(dg[4], (e3 - e2) - e4, (h[3] >> 8) & 0xffu);
+    dg[0] = dither_add(dg[0], T(-4) * e3, us);
+    dg[1] = dither_add(dg[1], (e3 + e1) + e4, us);
+    dg[2] = dither_add(dg[2], (e3 + e2) - e4, us);
+    dg[3] = dither_add(dg[3], (e3 - e1) + e4, us);
+    dg[4] = dither_add(dg[4], (e3 - e2) - e4, us);
   } else {
     const T c0 = dT * T(0.2), c1 = ns1 * T(0.5), c2 = ns2 * T(0.5);
     const T c3 = ns3 * T(0.05), c4 = ns4 * T(0.25);

@@ -155,7 +155,7 @@ template <typename S>
 hipError_t launch_adjoint(const KParams<S>& st, const AdjParams& a, int parity, const double* lam_next,
                           double* lam, double* g_logda, double* partial, hipStream_t s);
 hipError_t launch_adjoint_seed(int nx, int ny, double seed, double* lam, hipStream_t s);
-hipError_t launch_write_header(void* dst, int64_t steps, uint64_t tag, hipStream_t s);
+hipError_t launch_write_header(void* dst, int64_t steps, uint64_t tag, uint64_t phys, hipStream_t s);
 // Two time steps of an FP32 cavity (no periodic axis) in one pass, from the
 // natural-layout state in src (even step count) to dst.
 hipError_t launch_step2(const KParams<float>& src, const KParams<float>& dst, hipStream_t s, bool pow,

@@ -419,10 +419,11 @@ __global__ void k_convert(T* dst, const I* src, int64_t n) {
     dst[k] = (T)src[k];
 }
 
-__global__ void k_header(int64_t* dst, int64_t steps, uint64_t tag) {
+__global__ void k_header(int64_t* dst, int64_t steps, uint64_t tag, uint64_t phys) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     dst[0] = (int64_t)tag;
     dst[1] = steps;
+    dst[2] = (int64_t)phys;
   }
 }
 
@@ -692,8 +693,8 @@ hipError_t launch_set_logda(const KParams<T>& p, const Launch& L, T* dst, const 
   return hipGetLastError();
 }
 
-hipError_t launch_write_header(void* dst, int64_t steps, uint64_t tag, hipStream_t s) {
-  hipLaunchKernelGGL(k_header, dim3(1), dim3(64), 0, s, (int64_t*)dst, steps, tag);
+hipError_t launch_write_header(void* dst, int64_t steps, uint64_t tag, uint64_t phys, hipStream_t s) {
+  hipLaunchKernelGGL(k_header, dim3(1), dim3(64), 0, s, (int64_t*)dst, steps, tag, phys);
   return hipGetLastError();
 }
 

@@ -288,6 +288,38 @@ def test_checkpoint_resume_is_bitwise():
     c = gpu_for(40, dtype="fp32", **kw)
     with pytest.raises(Exception):
         c.load_state(snap)
+    # a state saved with other physics is refused (PM_ESTATE) and nothing is loaded
+    d = gpu_for(48, dtype="fp32", **dict(kw, n=0.8))
+    f0, g0 = d.populations(torch.float32)
+    with pytest.raises(P.PmError, match="other physics") as ei:
+        d.load_state(snap)
+    assert ei.value.code == -4 and d.steps == 0
+    fd, gd = d.populations(torch.float32)
+    assert torch.equal(f0, fd) and torch.equal(g0, gd)
+    # the same physics with the default rates given explicitly loads
+    e = gpu_for(48, dtype="fp32", s_e=1.4, s_eps=1.4, s_q=1.2, **kw)
+    e.load_state(snap)
+    assert e.steps == 777
+
+
+def test_checkpoint_keeps_the_residual_snapshot():
+    """A checkpoint taken between two residual checks carries the snapshot of
+    the last check, so the next check after a resume equals the uninterrupted
+    run's, at the same step."""
+    kw = dict(n=0.8, Da=1e-2, Ra=1e4, Pr=10.0, eps=0.6)
+    a = gpu_for(40, dtype="fp64", **kw)
+    a.step(1000)
+    r1, at1 = a.residual(with_step=True)
+    assert at1 == 1000 and r1 > 0
+    a.step(300)
+    snap = a.save_state()
+    a.step(700)
+    ra, sa = a.residual(with_step=True)
+    b = gpu_for(40, dtype="fp64", **kw)
+    b.load_state(snap)
+    b.step(700)
+    rb, sb = b.residual(with_step=True)
+    assert (ra, sa) == (rb, sb) and sa == 2000
 
 
 def test_runs_are_deterministic():

@@ -64,6 +64,29 @@ def test_sweep_stops_cases_at_their_own_steps():
     assert steps2 == steps
 
 
+@pytest.mark.parametrize("check,cap", [(500, 1700), (400, 399)])
+def test_sweep_cap_not_a_multiple_of_the_check(check, cap):
+    """A cap that is not a multiple of the check interval: the chunk that
+    reaches it is shortened, so every case stops at exactly the cap, with the
+    residual of that chunk, bitwise equal to run_to_steady alone."""
+    cases = [dict(c, dtype="fp32") for c in CASES[:3]]
+    sw = P.Sweep(cases)
+    steps, res = sw.run(tol=1e-14, check_every=check, max_steps=cap)
+    assert steps == [cap] * len(cases)
+    for i, kw in enumerate(CASES[:3]):
+        kw = dict(kw)
+        nx, ny = kw.pop("nx"), kw.pop("ny", None)
+        alone = P.Cavity(nx, ny, dtype="fp32", **kw)
+        r_alone, s_alone = alone.run_to_steady(tol=1e-14, check_every=check, max_steps=cap)
+        assert s_alone == cap and res[i] == r_alone
+        fa, ga = alone.populations(torch.float32)
+        fb, gb = sw.case(i).populations(torch.float32)
+        assert torch.equal(fa, fb) and torch.equal(ga, gb), i
+    # the cap counts steps since creation: a later run takes none
+    steps2, res2 = sw.run(tol=1e-14, check_every=check, max_steps=cap)
+    assert steps2 == steps and res2 == res
+
+
 def test_sweep_case_matches_oracle():
     """A well-conditioned case (tau >= 0.6 everywhere) of a two-case FP64
     sweep against the oracle after 1500 steps."""
