@@ -348,6 +348,19 @@ size_t pm_adjoint_vjp_scratch_bytes(const pm_ctx* ctx);
 int pm_adjoint_vjp(pm_ctx* ctx, const void* lam_next, void* lam, void* grad_logda, void* dev_scratch,
                    size_t scratch_bytes, double* grad_scalars);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the adjoint
+ * step of pm_adjoint_vjp, with the same arguments except the scratch buffer
+ * and bit-for-bit the same results.  Its per-workgroup partial sums live in a
+ * static device array of the library instead (2 MiB + 32 B on each device
+ * that calls it, held until the process ends), which it clears with a kernel
+ * on every call.  Limit: ceil(nx / 256) * ny <= 65536 workgroups (4096^2
+ * fits); larger grids get PM_EINVAL and a message.  The context's device must
+ * be current (else PM_EINVAL).  Every call on a device shares that device's
+ * array, so calls that overlap on one GPU (several threads or streams) race.
+ * Calls no hipMalloc, hipFree or other allocating routine.  Synchronises. */
+int pm_adjoint_vjp_noalloc(pm_ctx* ctx, const void* lam_next, void* lam, void* grad_logda,
+                           double* grad_scalars);
 
 const char* pm_strerror(int code);
 const char* pm_last_error(const pm_ctx* ctx);

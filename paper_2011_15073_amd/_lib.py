@@ -32,7 +32,7 @@ EXPORTS = [
     "pm_sweep_step", "pm_sweep_case", "pm_sweep_destroy", "pm_sweep_last_error",
     "pm_adjoint_workspace_bytes", "pm_adjoint_create", "pm_adjoint_forward",
     "pm_adjoint_backward", "pm_adjoint_set_shear_floor", "pm_adjoint_destroy", "pm_adjoint_last_error",
-    "pm_adjoint_vjp_scratch_bytes", "pm_adjoint_vjp",
+    "pm_adjoint_vjp_scratch_bytes", "pm_adjoint_vjp", "pm_adjoint_vjp_noalloc",
     "pm_strerror", "pm_last_error",
 ]
 
@@ -116,6 +116,7 @@ def _load():
         "pm_adjoint_last_error": ([vp], C.c_char_p),
         "pm_adjoint_vjp_scratch_bytes": ([vp], sz),
         "pm_adjoint_vjp": ([vp, vp, vp, vp, vp, sz, P(dbl)], i32),
+        "pm_adjoint_vjp_noalloc": ([vp, vp, vp, vp, P(dbl)], i32),
         "pm_strerror": ([i32], C.c_char_p),
         "pm_last_error": ([vp], C.c_char_p),
     }

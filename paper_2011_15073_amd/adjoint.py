@@ -108,3 +108,18 @@ def vjp_step(cavity: Cavity, lam_next):
                              C.c_void_p(g_ld.data_ptr()) if g_ld is not None else None,
                              C.c_void_p(scratch.data_ptr()), nbytes, gs), cavity._h)
     return lam, g_ld, gs[0], gs[1]
+
+
+def vjp_step_noalloc(cavity: Cavity, lam_next, lam=None, grad_logda=None):
+    """``vjp_step`` through the allocation-free entry point: the library keeps
+    the partial sums in its own static device array, so no scratch buffer is
+    passed (and none is allocated if ``lam`` and ``grad_logda`` are given)."""
+    if lam is None:
+        lam = torch.empty_like(lam_next)
+    if grad_logda is None and cavity.params.has_logda:
+        grad_logda = torch.zeros((cavity.ny, cavity.nx), dtype=torch.float64, device=cavity.device)
+    gs = (C.c_double * 2)()
+    check(lib.pm_adjoint_vjp_noalloc(cavity._h, C.c_void_p(lam_next.data_ptr()), C.c_void_p(lam.data_ptr()),
+                                     C.c_void_p(grad_logda.data_ptr()) if grad_logda is not None else None,
+                                     gs), cavity._h)
+    return lam, grad_logda, gs[0], gs[1]

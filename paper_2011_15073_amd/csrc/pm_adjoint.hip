@@ -469,7 +469,41 @@ __global__ void k_adjoint_seed(int nx, int ny, double seed, double* __restrict__
   }
 }
 
+__global__ __launch_bounds__(256) void k_fill_zero(double* __restrict__ a, int64_t n) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+    a[t] = 0.0;
+}
+
+// The per-workgroup adjoint partials reduced in workgroup order, as the host
+// reduces them: out[q] = sum_b partial[b][q] for q < 3, out[3] = max_b
+// partial[b][3] with a NaN turning it to +inf.  One thread per component, so
+// the sums are added in exactly that order.
+__global__ void k_adj_reduce(const double* __restrict__ partial, int nblocks, double* __restrict__ out) {
+  const int q = threadIdx.x;
+  if (q >= ADJ_PART) return;
+  double acc = 0.0;
+  for (int b = 0; b < nblocks; ++b) {
+    const double m = partial[ADJ_PART * (int64_t)b + q];
+    if (q < 3) acc += m;
+    else acc = (m != m) ? INFINITY : (acc < m ? m : acc);
+  }
+  out[q] = acc;
+}
+
 }  // namespace
+
+hipError_t launch_fill_zero(double* a, int64_t n, hipStream_t s) {
+  int64_t b = (n + 255) / 256;
+  if (b > 4096) b = 4096;
+  if (b < 1) b = 1;
+  hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)b), dim3(256), 0, s, a, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_reduce(const double* partial, int nblocks, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_adj_reduce, dim3(1), dim3(64), 0, s, partial, nblocks, out);
+  return hipGetLastError();
+}
 
 template <typename S>
 hipError_t launch_adjoint(const KParams<S>& st, const AdjParams& a, int parity, const double* lam_next,

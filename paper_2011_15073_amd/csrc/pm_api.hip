@@ -13,6 +13,7 @@
 #include <new>
 #include <algorithm>
 #include <climits>
+#include <mutex>
 #include <type_traits>
 #include <vector>
 
@@ -1554,6 +1555,82 @@ int pm_adjoint_vjp(pm_ctx* c, const void* lam_next, void* lam, void* grad_logda,
   double sums[3], lam_max;
   reduce_partials(part, sums, lam_max);
   if (grad_scalars) chain_scalars(c, sums, &grad_scalars[0], &grad_scalars[1]);
+  return PM_OK;
+}
+
+}  // extern "C"
+
+// ---- allocation-free adjoint step ----
+// The per-workgroup partials of pm_adjoint_vjp_noalloc live in this
+// file-scope device array instead of caller scratch: ADJ_PART doubles for
+// each of up to NOALLOC_MAX_WG workgroups, then the ADJ_PART reduced values
+// (2 MiB + 32 B on each device, held until the process ends).  Host code
+// never passes the array's name to a kernel: it takes the array's device
+// address once per device with hipGetSymbolAddress and uses that.
+namespace {
+
+constexpr int NOALLOC_MAX_WG = 65536;
+constexpr size_t NOALLOC_OUT = (size_t)pm::ADJ_PART * NOALLOC_MAX_WG;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+
+static __device__ __align__(256) double scratch[NOALLOC_OUT + pm::ADJ_PART];
+
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[NOALLOC_MAX_DEVICES];  // device address of scratch, per device
+
+// The address of this device's copy of scratch (looked up on the first call
+// on the device, which must be current).
+int noalloc_scratch(pm_ctx* c, double** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return check_hip(c, e, "pm_adjoint_vjp_noalloc: hipGetDevice");
+  if (dev != c->device)
+    return ctx_fail(c, PM_EINVAL, "pm_adjoint_vjp_noalloc: make the context's device (%d) current, not %d",
+                    c->device, dev);
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+    return ctx_fail(c, PM_EINVAL, "pm_adjoint_vjp_noalloc: device %d beyond the %d supported", dev,
+                    NOALLOC_MAX_DEVICES);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return check_hip(c, e != hipSuccess ? e : hipErrorInvalidSymbol,
+                                                  "pm_adjoint_vjp_noalloc: hipGetSymbolAddress");
+    g_scratch_ptr[dev] = (double*)ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return PM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pm_adjoint_vjp_noalloc(pm_ctx* c, const void* lam_next, void* lam, void* grad_logda, double* grad_scalars) {
+  if (!c || !lam_next || !lam) return PM_EINVAL;
+  if (c->p.periodic_x || c->p.periodic_y || c->p.clamp_mode != PM_CLAMP_NU || c->p.gx != 0.0 || c->p.gy != 0.0)
+    return ctx_fail(c, PM_EINVAL, "pm_adjoint_vjp_noalloc: cavity walls, PM_CLAMP_NU and no body force only");
+  if (c->p.has_logda && !grad_logda) return ctx_fail(c, PM_EINVAL, "pm_adjoint_vjp_noalloc: grad_logda needed");
+  const int nblocks = c->launch.ntiles;
+  if (nblocks > NOALLOC_MAX_WG)
+    return ctx_fail(c, PM_EINVAL,
+                    "pm_adjoint_vjp_noalloc: the grid needs %d workgroup slots, the static scratch holds %d "
+                    "(ceil(nx / %d) * ny must not exceed it); use pm_adjoint_vjp with caller scratch",
+                    nblocks, NOALLOC_MAX_WG, pm::TILE);
+  double* ptr = nullptr;
+  int rc = noalloc_scratch(c, &ptr);
+  if (rc) return rc;
+  hipError_t e = pm::launch_fill_zero(ptr, (int64_t)pm::ADJ_PART * nblocks, c->stream);
+  if (e == hipSuccess)
+    e = adj_step(c, adj_params(c), (char*)c->ws + c->lay.off_f, (int)(c->steps & 1), (const double*)lam_next,
+                 (double*)lam, (double*)grad_logda, ptr);
+  if (e == hipSuccess) e = pm::launch_adj_reduce(ptr, nblocks, ptr + NOALLOC_OUT, c->stream);
+  double out[pm::ADJ_PART];
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(out, ptr + NOALLOC_OUT, sizeof out, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return check_hip(c, e, "pm_adjoint_vjp_noalloc");
+  if (grad_scalars) chain_scalars(c, out, &grad_scalars[0], &grad_scalars[1]);
   return PM_OK;
 }
 

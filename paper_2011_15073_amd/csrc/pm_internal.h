@@ -155,6 +155,10 @@ template <typename S>
 hipError_t launch_adjoint(const KParams<S>& st, const AdjParams& a, int parity, const double* lam_next,
                           double* lam, double* g_logda, double* partial, hipStream_t s);
 hipError_t launch_adjoint_seed(int nx, int ny, double seed, double* lam, hipStream_t s);
+// a[0, n) := 0 (a fill kernel, so that callers may capture it in a graph)
+hipError_t launch_fill_zero(double* a, int64_t n, hipStream_t s);
+// the adjoint partials of nblocks workgroups reduced in workgroup order into out[ADJ_PART]
+hipError_t launch_adj_reduce(const double* partial, int nblocks, double* out, hipStream_t s);
 hipError_t launch_write_header(void* dst, int64_t steps, uint64_t tag, uint64_t phys, hipStream_t s);
 // Two time steps of an FP32 cavity (no periodic axis) in one pass, from the
 // natural-layout state in src (even step count) to dst.
