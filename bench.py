@@ -46,7 +46,7 @@ PHYS = dict(n=0.8, Da=1e-2, Ra=1e5, Pr=10.0, eps=0.6)
 BYTES_PER_NODE = 112  # 14 FP32 populations, each read once and written once per step
 HBM_PEAK_GBS = 8000.0
 CHECK_EVERY = 1000
-DEFAULT_ROUNDING = "nearest"  # the library's default for FP32 (pm_params_default)
+DEFAULT_ROUNDING = "stochastic"  # the library's default for FP32 (PM_ROUND_AUTO)
 CSRC = os.path.join(ROOT, "paper_2011_15073_amd", "csrc")
 # The step kernels the benchmark can time (--step-kernel; the default "auto"
 # takes the two-step kernel at 4096^2), each with its committed counter
@@ -68,6 +68,14 @@ KERNELS = {
               (os.path.join(CSRC, "pm_kernels.hip"), r"// ---- two time steps in one pass.*?(?=// ---- )"),
               (os.path.join(CSRC, "pm_kernels.hip"), r"hipError_t launch_step2\(.*?\n}\n"),
               (os.path.join(CSRC, "pm_api.hip"), r"int pair_rows_for\(.*?\n}\n")]),
+    "single_sr": dict(
+        name="k_step SR (one fused stream+collide step per launch, stochastically rounded updates)",
+        steps_per_launch=1,
+        traffic_file=os.path.join(ROOT, "profiles", "k_step_fp32sr_4096_traffic.txt"),
+        srcs=[os.path.join(CSRC, "pm_device.h"), os.path.join(CSRC, "pm_internal.h"),
+              (os.path.join(CSRC, "pm_kernels.hip"), r"void k_step\(KParams<T> p.*?\n}\n"),
+              (os.path.join(CSRC, "pm_kernels.hip"), r"hipError_t launch_step\(.*?\n}\n"),
+              (os.path.join(CSRC, "pm_api.hip"), r"int step_width_for\(.*?\n}\n")]),
     "single_fp64": dict(
         name="k_step FP64 (one fused stream+collide step per launch, AA pattern in place)", steps_per_launch=1,
         traffic_file=os.path.join(ROOT, "profiles", "k_step_fp64_4096_traffic.txt"),
@@ -208,7 +216,7 @@ def sweep_main(args):
     log(f"sweep: batched {t_batched:.2f} s, {nupd / t_batched / 1e6:.0f} MLUPS")
     t_seq, same = 0.0, 0
     tdt = torch.float64 if dt == "fp64" else torch.float32
-    for i, (kw, c) in enumerate(zip(cases, cs)):
+    for i, (kw, c) in enumerate(zip(cases, cs) if not args.sweep_no_sequential else []):
         kw = dict(kw)
         nx = kw.pop("nx")
         cav = P.Cavity(nx, **kw)
@@ -233,9 +241,9 @@ def sweep_main(args):
                                "{128,192,256,384,512} (seed 0)", "tol": args.sweep_tol,
                    "check_every": 1000, "max_steps": args.sweep_cap,
                    "schedule": {"order": sched["order"], "tile": list(sched["tile"])}},
-        "batched_s": round(t_batched, 3), "sequential_s": round(t_seq, 3),
-        "sequential_cases_per_s": round(len(cases) / t_seq, 4),
-        "speedup_vs_sequential": round(t_seq / t_batched, 3),
+        "batched_s": round(t_batched, 3), "sequential_s": round(t_seq, 3) if t_seq else None,
+        "sequential_cases_per_s": round(len(cases) / t_seq, 4) if t_seq else None,
+        "speedup_vs_sequential": round(t_seq / t_batched, 3) if t_seq else None,
         "node_updates": nupd, "batched_MLUPS": round(nupd / t_batched / 1e6, 1),
         "cases_bitwise_equal_to_sequential": f"{same}/{len(cases)}",
         "steps_per_case": steps}), flush=True)
@@ -396,6 +404,8 @@ def main():
     ap.add_argument("--sweep-dtype", default="fp64", choices=["fp32", "fp64"])
     ap.add_argument("--sweep-tol", type=float, default=1e-8)
     ap.add_argument("--sweep-cap", type=int, default=3_000_000)
+    ap.add_argument("--sweep-no-sequential", action="store_true",
+                    help="time only the batched sweep (no sequential runs, no bitwise comparison)")
     ap.add_argument("--paper-tables", action="store_true",
                     help="run the paper's validation and parametric cases and print Nu beside its values")
     ap.add_argument("--paper-side", type=int, default=160)

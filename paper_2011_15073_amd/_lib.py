@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libpmlbm.so")
 PM_OK, PM_EINVAL, PM_EDEVICE, PM_EDIVERGED, PM_ESTATE = 0, -1, -2, -3, -4
 PM_FP32, PM_FP64 = 0, 1
 PM_CLAMP_NU, PM_CLAMP_GAMMA = 0, 1
-PM_ROUND_NEAREST, PM_ROUND_STOCHASTIC = 0, 1
+PM_ROUND_NEAREST, PM_ROUND_STOCHASTIC, PM_ROUND_AUTO = 0, 1, 2
 
 # every symbol the header declares, in declaration order
 EXPORTS = [
@@ -144,7 +144,7 @@ def check(rc, ctx=None, errfn=None):
 def make_params(nx, ny=None, *, n=1.0, Da=math.inf, Ra=1e3, Pr=10.0, eps=1.0, mach=0.1,
                 nu_lo=0.1, nu_hi=10.0, clamp_mode=PM_CLAMP_NU, dtype="fp32", forchheimer=1,
                 has_logda=0, s_e=0.0, s_eps=0.0, s_q=0.0, sT_e=0.0, sT_nu=0.0, gx=0.0, gy=0.0,
-                T_init=0.5, periodic_x=0, periodic_y=0, step_kernel=0, rounding="nearest") -> PmParams:
+                T_init=0.5, periodic_x=0, periodic_y=0, step_kernel=0, rounding="auto") -> PmParams:
     p = PmParams()
     check(lib.pm_params_default(C.byref(p)))
     p.nx, p.ny = int(nx), int(nx if ny is None else ny)
@@ -156,8 +156,9 @@ def make_params(nx, ny=None, *, n=1.0, Da=math.inf, Ra=1e3, Pr=10.0, eps=1.0, ma
     p.s_e, p.s_eps, p.s_q, p.sT_e, p.sT_nu = s_e, s_eps, s_q, sT_e, sT_nu
     p.gx, p.gy, p.T_init = gx, gy, T_init
     p.step_kernel = {"auto": 0, "single": 1, "pair": 2, 0: 0, 1: 1, 2: 2}[step_kernel]
-    p.rounding = {"nearest": PM_ROUND_NEAREST, "stochastic": PM_ROUND_STOCHASTIC,
-                  PM_ROUND_NEAREST: PM_ROUND_NEAREST, PM_ROUND_STOCHASTIC: PM_ROUND_STOCHASTIC}[rounding]
+    p.rounding = {"nearest": PM_ROUND_NEAREST, "stochastic": PM_ROUND_STOCHASTIC, "auto": PM_ROUND_AUTO,
+                  PM_ROUND_NEAREST: PM_ROUND_NEAREST, PM_ROUND_STOCHASTIC: PM_ROUND_STOCHASTIC,
+                  PM_ROUND_AUTO: PM_ROUND_AUTO}[rounding]
     return p
 
 

@@ -140,6 +140,12 @@ Layout layout_of(const pm_params& p, bool pair = false) {
   return L;
 }
 
+// FP32 population updates are rounded stochastically (PM_ROUND_STOCHASTIC, or
+// the default PM_ROUND_AUTO with FP32 storage).
+bool rounds_stochastically(const pm_params& p) {
+  return p.dtype == PM_FP32 && (p.rounding == PM_ROUND_STOCHASTIC || p.rounding == PM_ROUND_AUTO);
+}
+
 // Step 0 of the update: physical groups -> lattice values (see pmlbm.h).
 int map_params(const pm_params& p, pm_lattice& L, char* msg, size_t msglen) {
   auto fail = [&](const char* m) {
@@ -170,8 +176,8 @@ int map_params(const pm_params& p, pm_lattice& L, char* msg, size_t msglen) {
     return fail("PM_STEP_PAIR needs FP32 and cavity walls on both axes");
   if (p.step_kernel == PM_STEP_PAIR && (p.ny + pm::PAIR_R - 1) / pm::PAIR_R > pm::GRID_Y_MAX)
     return fail("PM_STEP_PAIR: ny too large (more row groups than a launch's y dimension takes)");
-  if (p.rounding != PM_ROUND_NEAREST && p.rounding != PM_ROUND_STOCHASTIC)
-    return fail("rounding must be PM_ROUND_NEAREST or PM_ROUND_STOCHASTIC");
+  if (p.rounding != PM_ROUND_NEAREST && p.rounding != PM_ROUND_STOCHASTIC && p.rounding != PM_ROUND_AUTO)
+    return fail("rounding must be PM_ROUND_AUTO, PM_ROUND_NEAREST or PM_ROUND_STOCHASTIC");
   if (p.rounding == PM_ROUND_STOCHASTIC && p.dtype != PM_FP32)
     return fail("PM_ROUND_STOCHASTIC applies to FP32 storage only");
   const double N = (double)p.nx;
@@ -239,7 +245,7 @@ pm::KParams<T> kparams(const pm_params& p, const pm_lattice& L, void* ws, const 
   k.inv_n = (T)(1.0 / p.n);
   k.tol = sizeof(T) == 8 ? (T)1e-13 : (T)8e-6;
   k.max_it = sizeof(T) == 8 ? 40 : 12;
-  k.sr = (sizeof(T) == 4 && p.rounding == PM_ROUND_STOCHASTIC) ? 1 : 0;
+  k.sr = (sizeof(T) == 4 && rounds_stochastically(p)) ? 1 : 0;
   k.eps = (T)L.eps;
   k.inv_eps = (T)(1.0 / L.eps);
   k.invK = std::isinf(L.K) ? (T)0 : (T)(1.0 / L.K);
@@ -382,7 +388,7 @@ uint64_t physics_hash(const pm_ctx* c) {
   const pm_lattice& L = c->L;
   const double d[] = {c->p.n, L.U_lb, L.nu0, L.nu_min, L.nu_max, L.gamma_scale, L.eps, L.K, L.Feps, L.gbeta,
                       L.alpha, L.s_e, L.s_eps, L.s_q, L.sT_e, L.sT_nu, c->p.gx, c->p.gy};
-  const int32_t k[] = {c->p.has_logda, c->p.periodic_x, c->p.periodic_y, c->p.rounding};
+  const int32_t k[] = {c->p.has_logda, c->p.periodic_x, c->p.periodic_y, rounds_stochastically(c->p) ? 1 : 0};
   eat(d, sizeof d);
   eat(k, sizeof k);
   return h;
@@ -412,6 +418,7 @@ int pm_params_default(pm_params* p) {
   p->dtype = PM_FP32;
   p->forchheimer = 1;
   p->T_init = 0.5;
+  p->rounding = PM_ROUND_AUTO;
   return PM_OK;
 }
 
@@ -755,6 +762,8 @@ struct pm_sweep {
   std::vector<pm_ctx*> ctx;
   std::vector<int> ntiles, tile_base;
   int total_tiles;
+  int nsched;           // schedule entries: the tiles of the cases live when it was built
+  int sched_live;       // cases live when the schedule was built
   int tile_w, tile_h;   // sweep tile: tile_w columns by tile_h rows (pm_sweep_set_tile)
   bool any_sr;          // some case rounds stochastically (PM_ROUND_STOCHASTIC)
   void* d_cases;        // SweepCase<T>[ncases]
@@ -836,24 +845,30 @@ int sweep_fail(pm_sweep* s, int code, const char* fmt, ...) {
   return code;
 }
 
+// Only the tiles of live cases are scheduled, so cases that have stopped cost
+// no workgroups (the step kernel still checks the live flag).
 void build_schedule(pm_sweep* s) {
   const int n = s->ncases;
-  std::vector<int> ids(n);
-  for (int i = 0; i < n; ++i) ids[i] = i;
+  auto live = [&](int i) { return s->h_live.empty() || s->h_live[i] != 0; };
+  std::vector<int> ids;
+  for (int i = 0; i < n; ++i)
+    if (live(i)) ids.push_back(i);
+  s->sched_live = (int)ids.size();
   if (s->order == PM_ORDER_LARGEST)
     std::stable_sort(ids.begin(), ids.end(), [&](int a, int b) { return s->ntiles[a] > s->ntiles[b]; });
   s->h_sched.clear();
   s->h_sched.reserve(s->total_tiles);
   if (s->order == PM_ORDER_INTERLEAVE) {
     int maxt = 0;
-    for (int i = 0; i < n; ++i) maxt = std::max(maxt, s->ntiles[i]);
+    for (int i : ids) maxt = std::max(maxt, s->ntiles[i]);
     for (int t = 0; t < maxt; ++t)
-      for (int i = 0; i < n; ++i)
+      for (int i : ids)
         if (t < s->ntiles[i]) s->h_sched.push_back(make_int2(i, t));
   } else {
     for (int i : ids)
       for (int t = 0; t < s->ntiles[i]; ++t) s->h_sched.push_back(make_int2(i, t));
   }
+  s->nsched = (int)s->h_sched.size();
 }
 
 hipError_t sweep_enqueue_chunk(pm_sweep* s, hipStream_t st, int64_t chunk, int parity0, double tol,
@@ -863,19 +878,19 @@ hipError_t sweep_enqueue_chunk(pm_sweep* s, hipStream_t st, int64_t chunk, int p
     const int par = (int)((parity0 + t) & 1);
     if (s->dtype == PM_FP64)
       e = pm::launch_step_multi<double>((const pm::SweepCase<double>*)s->d_cases, s->d_sched, s->d_live,
-                                        s->total_tiles, par, s->tile_w, s->tile_h, s->any_sr, st);
+                                        s->nsched, par, s->tile_w, s->tile_h, s->any_sr, st);
     else
       e = pm::launch_step_multi<float>((const pm::SweepCase<float>*)s->d_cases, s->d_sched, s->d_live,
-                                       s->total_tiles, par, s->tile_w, s->tile_h, s->any_sr, st);
+                                       s->nsched, par, s->tile_w, s->tile_h, s->any_sr, st);
   }
   if (e != hipSuccess) return e;
   const int par_end = (int)((parity0 + chunk) & 1);
   if (s->dtype == PM_FP64)
     return pm::launch_resid_multi<double>((const pm::SweepCase<double>*)s->d_cases, s->ncases, s->d_sched,
-                                          s->d_live, s->total_tiles, par_end, s->tile_w, s->tile_h,
+                                          s->d_live, s->nsched, par_end, s->tile_w, s->tile_h,
                                           s->d_partial, s->d_st, chunk, tol, max_steps, st);
   return pm::launch_resid_multi<float>((const pm::SweepCase<float>*)s->d_cases, s->ncases, s->d_sched,
-                                       s->d_live, s->total_tiles, par_end, s->tile_w, s->tile_h, s->d_partial,
+                                       s->d_live, s->nsched, par_end, s->tile_w, s->tile_h, s->d_partial,
                                        s->d_st, chunk, tol, max_steps, st);
 }
 
@@ -991,7 +1006,7 @@ int pm_sweep_create(const pm_params* cases, int ncases, void* dev_ws, size_t ws_
   s->tile_h = 1;
   s->any_sr = false;
   for (int i = 0; i < ncases; ++i)
-    if (cases[i].rounding == PM_ROUND_STOCHASTIC) s->any_sr = true;
+    if (rounds_stochastically(cases[i])) s->any_sr = true;
   char* base = (char*)dev_ws;
   s->d_cases = base + L.off_cases;
   s->d_sched = (int2*)(base + L.off_sched);
@@ -1108,6 +1123,17 @@ int pm_sweep_advance(pm_sweep* s, double tol, int64_t check_every, int64_t max_s
     e = hipMemcpyAsync(s->h_live.data(), s->d_live, s->ncases * sizeof(int), hipMemcpyDeviceToHost, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) return sweep_fail(s, PM_EDEVICE, "pm_sweep_advance: %s", hipGetErrorString(e));
+    // cases stopped in this chunk: schedule only the live ones from now on
+    int now_live = 0;
+    for (int i = 0; i < s->ncases; ++i) now_live += s->h_live[i];
+    if (now_live && now_live < s->sched_live) {
+      build_schedule(s);
+      sweep_drop_graphs(s);
+      e = hipMemcpyAsync(s->d_sched, s->h_sched.data(), s->h_sched.size() * sizeof(int2), hipMemcpyHostToDevice,
+                         s->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+      if (e != hipSuccess) return sweep_fail(s, PM_EDEVICE, "pm_sweep_advance: %s", hipGetErrorString(e));
+    }
   }
   e = hipMemcpyAsync(s->h_st.data(), s->d_st, s->ncases * sizeof(pm::SweepStatus), hipMemcpyDeviceToHost,
                      s->stream);
@@ -1148,10 +1174,10 @@ int pm_sweep_step(pm_sweep* s, int64_t k) {
     const int par = (int)((s->gsteps + t) & 1);
     if (s->dtype == PM_FP64)
       e = pm::launch_step_multi<double>((const pm::SweepCase<double>*)s->d_cases, s->d_sched, s->d_live,
-                                        s->total_tiles, par, s->tile_w, s->tile_h, s->any_sr, s->stream);
+                                        s->nsched, par, s->tile_w, s->tile_h, s->any_sr, s->stream);
     else
       e = pm::launch_step_multi<float>((const pm::SweepCase<float>*)s->d_cases, s->d_sched, s->d_live,
-                                       s->total_tiles, par, s->tile_w, s->tile_h, s->any_sr, s->stream);
+                                       s->nsched, par, s->tile_w, s->tile_h, s->any_sr, s->stream);
   }
   if (e != hipSuccess) return sweep_fail(s, PM_EDEVICE, "pm_sweep_step: %s", hipGetErrorString(e));
   // live cases advance together; the per-case counters follow on the device

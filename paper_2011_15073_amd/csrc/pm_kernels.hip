@@ -583,6 +583,7 @@ template <typename T>
 hipError_t launch_step_multi(const SweepCase<T>* cases, const int2* sched, const int* live,
                              int nsched, int parity, int tw, int th, bool any_sr, hipStream_t s) {
   if (!sweep_tile_ok(tw, th)) return hipErrorInvalidValue;
+  if (nsched <= 0) return hipSuccess;  // no live case scheduled
 #define PM_MULTI(ODD, SR) \
   hipLaunchKernelGGL((k_step_multi<T, ODD, SR>), dim3(nsched), dim3(tw * th), 0, s, cases, sched, live, tw, th)
   bool sr = false;
@@ -604,6 +605,7 @@ hipError_t launch_resid_multi(const SweepCase<T>* cases, int ncases, const int2*
                               int nsched, int parity, int tw, int th, double* partial, SweepStatus* st,
                               int64_t chunk, double tol, int64_t max_steps, hipStream_t s) {
   if (!sweep_tile_ok(tw, th)) return hipErrorInvalidValue;
+  if (nsched <= 0) return hipSuccess;  // no live case scheduled
   hipLaunchKernelGGL((k_resid_multi<T>), dim3(nsched), dim3(tw * th), 0, s, cases, sched,
                      (const int*)live, parity, partial, tw, th);
   hipLaunchKernelGGL((k_retire<T>), dim3(1), dim3(64), 0, s, cases, ncases, (const double*)partial,

@@ -5,11 +5,12 @@ viscosity clamped to [0.1, 10] nu0, Da = 1e-3, Ra = 1e5, Pr = 10, eps = 0.6,
 from rest, run until max |dT| over 1000 steps < 1e-8 (checked every 1000
 steps).  Stored: the stopping step S*, the final residual, the hot-wall
 Nusselt number (Eq. 24), max |U|, max |V| over the whole field, the
-nondimensional fields U, V, theta on every 4th node in each direction, and
-U, V, theta on the two hot-wall columns.
+nondimensional fields U, V, theta at every node (FP64), and, as before,
+U, V, theta on every 4th node in each direction and on the two hot-wall
+columns.
 
 Run from the repository root:  python tests/golden/make_cfg1_golden.py [out.npz]
-(about ten minutes on 16 cores; the default output is the path above).
+(one to two hours on 8 cores; the default output is the path above).
 """
 import os
 import sys
@@ -42,6 +43,7 @@ def main():
     out = sys.argv[1] if len(sys.argv) > 1 else os.path.join(ROOT, "tests", "golden", "cfg1_256_oracle.npz")
     np.savez_compressed(out, steps=steps, residual=r, nu_bar=orc.nu_bar(),
                         maxU=np.abs(U).max(), maxV=np.abs(V).max(), maxT=np.abs(th).max(),
+                        U=U, V=V, T=th,
                         U4=U[::4, ::4], V4=V[::4, ::4], T4=th[::4, ::4],
                         Uw=U[:, :2], Vw=V[:, :2], Tw=th[:, :2],
                         phys=np.array(str(PHYS)))

@@ -70,7 +70,7 @@ def test_host_mapping_matches_oracle(case):
 @pytest.mark.parametrize("bad", [
     dict(nx=1), dict(eps=0.0), dict(eps=1.2), dict(n=0.0), dict(Ra=-1.0), dict(Da=0.0),
     dict(mach=0.0), dict(nu_lo=2.0), dict(nu_lo=0.5, nu_hi=0.4), dict(dtype=7),
-    dict(s_q=2.5), dict(rounding=2), dict(rounding=1, dtype=1),
+    dict(s_q=2.5), dict(rounding=3), dict(rounding=1, dtype=1),
 ])
 def test_invalid_parameters_are_rejected(bad):
     p = P.make_params(32)
