@@ -73,21 +73,29 @@ KERNELS = {
         steps_per_launch=1,
         traffic_file=os.path.join(ROOT, "profiles", "k_step_fp32sr_4096_traffic.txt"),
         srcs=[os.path.join(CSRC, "pm_device.h"), os.path.join(CSRC, "pm_internal.h"),
-              (os.path.join(CSRC, "pm_kernels.hip"), r"void k_step\(KParams<T> p.*?\n}\n"),
+              (os.path.join(CSRC, "pm_kernels.hip"), r"void k_step\(KParams<T, S> p.*?\n}\n"),
+              (os.path.join(CSRC, "pm_kernels.hip"), r"hipError_t launch_step\(.*?\n}\n"),
+              (os.path.join(CSRC, "pm_api.hip"), r"int step_width_for\(.*?\n}\n")]),
+    "single_fp16": dict(
+        name="k_step FP16 storage (one fused stream+collide step per launch, half-precision populations, "
+             "FP32 arithmetic, stochastically rounded stores)", steps_per_launch=1,
+        traffic_file=os.path.join(ROOT, "profiles", "k_step_fp16_4096_traffic.txt"),
+        srcs=[os.path.join(CSRC, "pm_device.h"), os.path.join(CSRC, "pm_internal.h"),
+              (os.path.join(CSRC, "pm_kernels.hip"), r"void k_step\(KParams<T, S> p.*?\n}\n"),
               (os.path.join(CSRC, "pm_kernels.hip"), r"hipError_t launch_step\(.*?\n}\n"),
               (os.path.join(CSRC, "pm_api.hip"), r"int step_width_for\(.*?\n}\n")]),
     "single_fp64": dict(
         name="k_step FP64 (one fused stream+collide step per launch, AA pattern in place)", steps_per_launch=1,
         traffic_file=os.path.join(ROOT, "profiles", "k_step_fp64_4096_traffic.txt"),
         srcs=[os.path.join(CSRC, "pm_device.h"), os.path.join(CSRC, "pm_internal.h"),
-              (os.path.join(CSRC, "pm_kernels.hip"), r"void k_step\(KParams<T> p.*?\n}\n"),
+              (os.path.join(CSRC, "pm_kernels.hip"), r"void k_step\(KParams<T, S> p.*?\n}\n"),
               (os.path.join(CSRC, "pm_kernels.hip"), r"hipError_t launch_step\(.*?\n}\n"),
               (os.path.join(CSRC, "pm_api.hip"), r"int step_width_for\(.*?\n}\n")]),
     "single": dict(
         name="k_step (one fused stream+collide step per launch, AA pattern in place)", steps_per_launch=1,
         traffic_file=os.path.join(ROOT, "profiles", "k_step_fp32_4096_traffic.txt"),
         srcs=[os.path.join(CSRC, "pm_device.h"), os.path.join(CSRC, "pm_internal.h"),
-              (os.path.join(CSRC, "pm_kernels.hip"), r"void k_step\(KParams<T> p.*?\n}\n"),
+              (os.path.join(CSRC, "pm_kernels.hip"), r"void k_step\(KParams<T, S> p.*?\n}\n"),
               (os.path.join(CSRC, "pm_kernels.hip"), r"hipError_t launch_step\(.*?\n}\n"),
               (os.path.join(CSRC, "pm_api.hip"), r"int step_width_for\(.*?\n}\n")]),
 }
@@ -257,16 +265,25 @@ def sweep_main(args):
 PAPER_TABLES = os.path.join(ROOT, "tests", "golden", "paper_nu_tables.json")
 
 
-def paper_cases(N):
+PAPER_CLAMPS = {
+    # the [0.1, 10] nu0 viscosity clamp of the 256^2 power-law workload
+    "nu": dict(clamp_mode=0, nu_lo=0.1, nu_hi=10.0),
+    # the paper's own modified power law, Eq. (21): gamma* clamped to [0.01, 1e6]
+    "gamma": dict(clamp_mode=1, nu_lo=0.01, nu_hi=1e6),
+}
+
+
+def paper_cases(N, clamp="nu", mach=0.1):
     """(sweep case, label dict, paper Nu) for every row of both tables."""
     tab = json.load(open(PAPER_TABLES))
+    extra = dict(PAPER_CLAMPS[clamp], mach=mach)
     out = []
     for r in tab["validation"]:
-        out.append((dict(nx=N, n=r["n"], Ra=r["Ra"], Pr=r["Pr"], eps=1.0, forchheimer=0, dtype="fp64"),
+        out.append((dict(nx=N, n=r["n"], Ra=r["Ra"], Pr=r["Pr"], eps=1.0, forchheimer=0, dtype="fp64", **extra),
                     dict(table="validation", n=r["n"], Da=None, Ra=r["Ra"], Pr=r["Pr"]), r["nu"]))
     for r in tab["parametric"]:
         out.append((dict(nx=N, n=r["n"], Da=r["Da"], Ra=r["Ra"], Pr=r["Pr"], eps=1.0, forchheimer=0,
-                         dtype="fp64"),
+                         dtype="fp64", **extra),
                     dict(table="parametric", n=r["n"], Da=r["Da"], Ra=r["Ra"], Pr=r["Pr"]), r["nu"]))
     return out
 
@@ -278,7 +295,7 @@ def paper_main(args):
     import paper_2011_15073_amd as P
 
     N = args.paper_side
-    rows_in = paper_cases(N)
+    rows_in = paper_cases(N, args.paper_clamp, args.paper_mach)
     cases = [c for c, _, _ in rows_in]
     sw = P.Sweep(cases)
     torch.cuda.synchronize()
@@ -295,7 +312,9 @@ def paper_main(args):
         log(f"paper: {par}: Nu {nu:.6f} (paper {nu_p}), {steps[i]} steps, r {res[i]:.1e}")
     print(json.dumps({"metric": "paper tables: Nu", "n_gpus": 1, "dtype": "f64", "data": "synthetic",
                       "config": {"workload": f"the paper's validation and parametric cases, {N}x{N}, "
-                                             "eps=1, Darcy drag only, Ma=0.1", "tol": args.sweep_tol,
+                                             f"eps=1, Darcy drag only, Ma={args.paper_mach}, "
+                                             f"viscosity clamp {args.paper_clamp} {PAPER_CLAMPS[args.paper_clamp]}",
+                                 "tol": args.sweep_tol,
                                  "max_steps": args.sweep_cap},
                       "wall_s": round(wall, 2), "cases": rows}), flush=True)
 
@@ -386,9 +405,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--step-kernel", default="auto", choices=["auto", "single", "pair"],
                     help="step kernel of the cavity (auto: the two-step kernel at 4096^2)")
-    ap.add_argument("--dtype", default="fp32", choices=["fp32", "fp64"],
+    ap.add_argument("--dtype", default="fp32", choices=["fp32", "fp64", "fp16"],
                     help="storage and arithmetic of the timed cavity (fp64: the single-step kernel, 224 B per "
-                         "node update)")
+                         "node update; fp16: half-precision population storage with FP32 arithmetic, the "
+                         "single-step kernel, 56 B per node update)")
     ap.add_argument("--rounding", default=None, choices=["nearest", "stochastic"],
                     help="rounding of the FP32 population updates (PM_ROUND_*; default: the library's)")
     ap.add_argument("--no-extras", action="store_true",
@@ -409,6 +429,10 @@ def main():
     ap.add_argument("--paper-tables", action="store_true",
                     help="run the paper's validation and parametric cases and print Nu beside its values")
     ap.add_argument("--paper-side", type=int, default=160)
+    ap.add_argument("--paper-clamp", default="gamma", choices=sorted(PAPER_CLAMPS),
+                    help="viscosity bounds of the paper's runs: the [0.1, 10] nu0 clamp, or Eq. (21)'s shear-rate "
+                         "thresholds 0.01 and 1e6")
+    ap.add_argument("--paper-mach", type=float, default=0.05, help="lattice Mach number of the paper's runs")
     ap.add_argument("--stream-function", action="store_true",
                     help="time the stream function of the 4096^2 workload")
     ap.add_argument("--adjoint", action="store_true",
@@ -441,17 +465,19 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     S, dt = args.side, args.dtype
-    rounding = args.rounding or ("stochastic" if dt == "fp32" and DEFAULT_ROUNDING == "stochastic" else "nearest")
+    rounding = args.rounding or ("stochastic" if dt in ("fp32", "fp16") and DEFAULT_ROUNDING == "stochastic"
+                                 else "nearest")
     kind, K = kernel_kind(P, S, dt, args.step_kernel, rounding)
     spl = K["steps_per_launch"]
-    bpn = BYTES_PER_NODE * (2 if dt == "fp64" else 1)
+    bpn = bytes_per_node(dt)
     log(f"bench: {S}x{S} {dt} {PHYS}, warmup {args.warmup}, steps {args.steps}, step kernel {args.step_kernel} "
         f"({K['name'].split()[0]}), rounding {rounding}")
     run = time_cavity(P, S, dt, rounding, args.step_kernel, args.warmup, args.steps, args.roofline_steps)
     mlups, ms_per_step, launch_s = run["mlups"], run["ms_per_step"], run["per_step_s"] * spl
     # algorithmic bytes of one launch of either step kernel: the launch reads
     # the whole state once and writes it once (the two-step kernel keeps its
-    # intermediate step on chip), 112 B (FP32) / 224 B (FP64) per node
+    # intermediate step on chip), 112 B (FP32) / 224 B (FP64) / 56 B (FP16
+    # storage) per node
     alg_launch = bpn * S * S
     achieved = alg_launch / launch_s / 1e9
     alg_equiv = bpn * S * S * spl / launch_s / 1e9  # the method's 112 B per node update
@@ -477,7 +503,8 @@ def main():
         "dtype": "f64" if dt == "fp64" else "f32",
         "data": "synthetic",
         "config": {"workload": f"porous power-law cavity {S}x{S}, D2Q9 MRT + D2Q5 MRT, "
-                               f"{dt.upper()} AA layout, n=0.8 Da=1e-2 Ra=1e5 Pr=10 eps=0.6, "
+                               f"{dt.upper()} {'storage (FP32 arithmetic) ' if dt == 'fp16' else ''}"
+                               "AA layout, n=0.8 Da=1e-2 Ra=1e5 Pr=10 eps=0.6, "
                                "Nu + residual on device every 1000 steps",
                    "nodes": S * S, "steps_timed": args.steps, "step_kernel": args.step_kernel,
                    "rounding": rounding},
@@ -498,7 +525,7 @@ def main():
     }
     del run
     torch.cuda.empty_cache()
-    if dt == "fp32" and not args.no_extras:
+    if dt in ("fp32", "fp16") and not args.no_extras:
         other = "nearest" if rounding == "stochastic" else "stochastic"
         kind_o, K_o = kernel_kind(P, S, dt, args.step_kernel, other)
         o = time_cavity(P, S, dt, other, args.step_kernel, args.warmup, args.steps, args.roofline_steps)
@@ -519,12 +546,18 @@ def main():
     print(json.dumps(result), flush=True)
 
 
+def bytes_per_node(dt):
+    """Algorithmic bytes per node update: 14 populations read once and written
+    once, 4 B each in FP32, 8 B in FP64, 2 B with FP16 storage."""
+    return {"fp32": BYTES_PER_NODE, "fp64": 2 * BYTES_PER_NODE, "fp16": BYTES_PER_NODE // 2}[dt]
+
+
 def kernel_kind(P, S, dt, step_kernel, rounding):
     """The step kernel the library will run (only the two-step kernel needs a
     second population region) and its entry in KERNELS."""
     pair = (P.workspace_bytes(P.make_params(S, dtype=dt, step_kernel=step_kernel, **PHYS)) >
             P.workspace_bytes(P.make_params(S, dtype=dt, step_kernel="single", **PHYS)))
-    kind = ("pair" if pair else "single") + ("_fp64" if dt == "fp64" else "")
+    kind = ("pair" if pair else "single") + {"fp64": "_fp64", "fp16": "_fp16"}.get(dt, "")
     if rounding == "stochastic" and kind + "_sr" in KERNELS:
         kind += "_sr"
     return kind, KERNELS[kind]

@@ -62,10 +62,11 @@ extern "C" {
 
 #define PM_FP32 0 /* FP32 storage and arithmetic; FP64 reductions */
 #define PM_FP64 1 /* FP64 storage and arithmetic */
+#define PM_FP16 2 /* FP16 population storage, FP32 arithmetic, FP64 reductions (see pm_params.dtype) */
 
 #define PM_ROUND_NEAREST 0    /* population updates rounded to nearest */
-#define PM_ROUND_STOCHASTIC 1 /* FP32 population updates rounded stochastically (see pm_params.rounding) */
-#define PM_ROUND_AUTO 2       /* default: stochastic with FP32 storage, nearest with FP64 */
+#define PM_ROUND_STOCHASTIC 1 /* FP32/FP16 population updates rounded stochastically (see pm_params.rounding) */
+#define PM_ROUND_AUTO 2       /* default: stochastic with FP32 and FP16 storage, nearest with FP64 */
 
 #define PM_STEP_AUTO 0   /* two-step kernel where it pays off (large FP32 cavities) */
 #define PM_STEP_SINGLE 1 /* always one step per pass (in place, AA pattern) */
@@ -89,7 +90,13 @@ typedef struct {
   double mach;     /* lattice Mach number (default 0.1) */
   double nu_lo, nu_hi; /* clamp bounds, see PM_CLAMP_* (default 0.1, 10) */
   int32_t clamp_mode;  /* PM_CLAMP_NU (default) or PM_CLAMP_GAMMA */
-  int32_t dtype;       /* PM_FP32 (default) or PM_FP64 */
+  int32_t dtype;       /* PM_FP32 (default), PM_FP64 or PM_FP16.  PM_FP16 stores the shifted
+                          populations as IEEE half (56 B per node update moved instead of 112),
+                          computes in FP32 and rounds every stored update stochastically (unless
+                          rounding = PM_ROUND_NEAREST); the per-cell planes stay FP32.  It runs the
+                          single-step kernel only, and neither sweeps nor the adjoint take it.
+                          Its fields are about 1e-3 of the FP64 oracle's after 20 000 steps of the
+                          64^2 cavities, against about 1e-6 for FP32. */
   int32_t forchheimer; /* 1 (default): Ergun F_eps; 0: Darcy-Brinkman only */
   int32_t has_logda;   /* 1: per-cell log10(Da) plane from pm_set_logda */
   double s_e, s_eps, s_q; /* D2Q9 rates s1, s2, s4 = s6 (default 1.4, 1.4, 1.2) */

@@ -19,7 +19,7 @@ _EXPORTS = {
     "Sweep": ".sweep", "tune": ".sweep",
     "Adjoint": ".adjoint", "nusselt": ".adjoint", "vjp_step": ".adjoint",
     "PmError": "._lib", "make_params": "._lib", "lattice_of": "._lib", "workspace_bytes": "._lib",
-    "PM_FP32": "._lib", "PM_FP64": "._lib", "PM_CLAMP_NU": "._lib", "PM_CLAMP_GAMMA": "._lib",
+    "PM_FP32": "._lib", "PM_FP64": "._lib", "PM_FP16": "._lib", "PM_CLAMP_NU": "._lib", "PM_CLAMP_GAMMA": "._lib",
 }
 
 __all__ = list(_EXPORTS)

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpmlbm.so")
 
 PM_OK, PM_EINVAL, PM_EDEVICE, PM_EDIVERGED, PM_ESTATE = 0, -1, -2, -3, -4
-PM_FP32, PM_FP64 = 0, 1
+PM_FP32, PM_FP64, PM_FP16 = 0, 1, 2
 PM_CLAMP_NU, PM_CLAMP_GAMMA = 0, 1
 PM_ROUND_NEAREST, PM_ROUND_STOCHASTIC, PM_ROUND_AUTO = 0, 1, 2
 
@@ -151,7 +151,8 @@ def make_params(nx, ny=None, *, n=1.0, Da=math.inf, Ra=1e3, Pr=10.0, eps=1.0, ma
     p.periodic_x, p.periodic_y = int(periodic_x), int(periodic_y)
     p.n, p.Da, p.Ra, p.Pr, p.eps, p.mach = n, Da, Ra, Pr, eps, mach
     p.nu_lo, p.nu_hi, p.clamp_mode = nu_lo, nu_hi, int(clamp_mode)
-    p.dtype = {"fp32": PM_FP32, "fp64": PM_FP64, PM_FP32: PM_FP32, PM_FP64: PM_FP64}[dtype]
+    p.dtype = {"fp32": PM_FP32, "fp64": PM_FP64, "fp16": PM_FP16, PM_FP32: PM_FP32, PM_FP64: PM_FP64,
+               PM_FP16: PM_FP16}[dtype]
     p.forchheimer, p.has_logda = int(forchheimer), int(has_logda)
     p.s_e, p.s_eps, p.s_q, p.sT_e, p.sT_nu = s_e, s_eps, s_q, sT_e, sT_nu
     p.gx, p.gy, p.T_init = gx, gy, T_init

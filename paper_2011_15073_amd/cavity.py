@@ -26,8 +26,9 @@ def _dt_code(dtype):
 class Cavity:
     """One simulation context (``pm_init`` ... ``pm_destroy``).
 
-    Parameters follow ``pm_params`` (pmlbm.h); ``dtype`` is ``"fp32"`` or
-    ``"fp64"``.  The context is bound to ``torch.cuda.current_stream(device)``
+    Parameters follow ``pm_params`` (pmlbm.h); ``dtype`` is ``"fp32"``,
+    ``"fp64"`` or ``"fp16"`` (half-precision population storage with FP32
+    arithmetic; fields and populations are still returned as FP32/FP64).  The context is bound to ``torch.cuda.current_stream(device)``
     at construction time.
     """
 

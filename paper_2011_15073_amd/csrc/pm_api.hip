@@ -38,7 +38,8 @@ constexpr size_t HEADER_BYTES = 256;
 size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
-  size_t elem;       // element size
+  size_t elem;       // population element size (2, 4 or 8 bytes)
+  size_t pelem;      // element size of the per-cell planes (the compute type: 4 or 8 bytes)
   size_t qs, rs;     // population stride, row stride (elements), see pm::KParams
   size_t plane;      // pitch of the per-cell planes (log10 Da, snapshot), elements
   size_t pop_bytes;  // the population region (f and g, padding included)
@@ -107,7 +108,8 @@ bool pair_capable(const pm_params& p) {
 
 Layout layout_of(const pm_params& p, bool pair = false) {
   Layout L{};
-  L.elem = p.dtype == PM_FP64 ? 8 : 4;
+  L.elem = p.dtype == PM_FP64 ? 8 : (p.dtype == PM_FP16 ? 2 : 4);
+  L.pelem = p.dtype == PM_FP64 ? 8 : 4;
   const size_t n = (size_t)p.nx * (size_t)p.ny;
   L.plane = (n + 63) / 64 * 64;
 #if PM_SOA_LAYOUT
@@ -124,9 +126,9 @@ Layout layout_of(const pm_params& p, bool pair = false) {
   L.off_g = o + 9 * L.qs * L.elem;
   o = align_up(o + L.pop_bytes);
   L.off_logda = o;
-  if (p.has_logda) o = align_up(o + L.plane * L.elem);
+  if (p.has_logda) o = align_up(o + L.plane * L.pelem);
   L.off_snap = o;
-  o = align_up(o + L.plane * L.elem);
+  o = align_up(o + L.plane * L.pelem);
   L.off_red = o;
   o = align_up(o + (pm::RED_BLOCKS + 16) * sizeof(double));
   L.off_scan = o;  // block sums of the stream-function scan
@@ -143,7 +145,8 @@ Layout layout_of(const pm_params& p, bool pair = false) {
 // FP32 population updates are rounded stochastically (PM_ROUND_STOCHASTIC, or
 // the default PM_ROUND_AUTO with FP32 storage).
 bool rounds_stochastically(const pm_params& p) {
-  return p.dtype == PM_FP32 && (p.rounding == PM_ROUND_STOCHASTIC || p.rounding == PM_ROUND_AUTO);
+  return (p.dtype == PM_FP32 || p.dtype == PM_FP16) &&
+         (p.rounding == PM_ROUND_STOCHASTIC || p.rounding == PM_ROUND_AUTO);
 }
 
 // Step 0 of the update: physical groups -> lattice values (see pmlbm.h).
@@ -157,7 +160,8 @@ int map_params(const pm_params& p, pm_lattice& L, char* msg, size_t msglen) {
   // the odd step's interior path addresses three rows of 14 populations with
   // 32-bit offsets: 42 padded rows must stay below 2^32 elements
   if (p.nx > 100000000) return fail("nx must be <= 1e8");
-  if (p.dtype != PM_FP32 && p.dtype != PM_FP64) return fail("dtype must be PM_FP32 or PM_FP64");
+  if (p.dtype != PM_FP32 && p.dtype != PM_FP64 && p.dtype != PM_FP16)
+    return fail("dtype must be PM_FP32, PM_FP64 or PM_FP16");
   if (!(p.n > 0.0 && p.n <= 4.0)) return fail("power-law index n must be in (0, 4]");
   if (!(p.Ra > 0.0) || !(p.Pr > 0.0)) return fail("Ra and Pr must be > 0");
   if (!(p.Da > 0.0)) return fail("Da must be > 0 (+inf for a clear fluid)");
@@ -178,8 +182,8 @@ int map_params(const pm_params& p, pm_lattice& L, char* msg, size_t msglen) {
     return fail("PM_STEP_PAIR: ny too large (more row groups than a launch's y dimension takes)");
   if (p.rounding != PM_ROUND_NEAREST && p.rounding != PM_ROUND_STOCHASTIC && p.rounding != PM_ROUND_AUTO)
     return fail("rounding must be PM_ROUND_AUTO, PM_ROUND_NEAREST or PM_ROUND_STOCHASTIC");
-  if (p.rounding == PM_ROUND_STOCHASTIC && p.dtype != PM_FP32)
-    return fail("PM_ROUND_STOCHASTIC applies to FP32 storage only");
+  if (p.rounding == PM_ROUND_STOCHASTIC && p.dtype == PM_FP64)
+    return fail("PM_ROUND_STOCHASTIC applies to FP32 and FP16 storage only");
   const double N = (double)p.nx;
   memset(&L, 0, sizeof L);
   L.U_lb = p.mach / std::sqrt(3.0);
@@ -219,12 +223,12 @@ int map_params(const pm_params& p, pm_lattice& L, char* msg, size_t msglen) {
   return PM_OK;
 }
 
-template <typename T>
-pm::KParams<T> kparams(const pm_params& p, const pm_lattice& L, void* ws, const Layout& lay) {
-  pm::KParams<T> k{};
+template <typename T, typename S = T>
+pm::KParams<T, S> kparams(const pm_params& p, const pm_lattice& L, void* ws, const Layout& lay) {
+  pm::KParams<T, S> k{};
   char* base = (char*)ws;
-  k.f = (T*)(base + lay.off_f);
-  k.g = (T*)(base + lay.off_g);
+  k.f = (S*)(base + lay.off_f);
+  k.g = (S*)(base + lay.off_g);
   k.logda = p.has_logda ? (const T*)(base + lay.off_logda) : nullptr;
   k.qs = (int64_t)lay.qs;
   k.rs = (int64_t)lay.rs;
@@ -282,6 +286,7 @@ struct pm_ctx {
   int64_t steps;
   pm::KParams<float> k32;
   pm::KParams<double> k64;
+  pm::KParams<float, _Float16> k16;  // FP16 storage, FP32 compute
   pm::KParams<float> k32b;  // k32 on the second population region (two-step kernel)
   bool pair;                // two-step kernel available (FP32 cavity, second region)
   int pair_rows;            // rows per workgroup of the two-step kernel
@@ -310,6 +315,7 @@ int check_hip(pm_ctx* c, hipError_t e, const char* what) {
 template <typename F>
 hipError_t dispatch(pm_ctx* c, F&& fn) {
   if (c->p.dtype == PM_FP64) return fn(c->k64);
+  if (c->p.dtype == PM_FP16) return fn(c->k16);
   return fn(c->k32);
 }
 
@@ -365,7 +371,7 @@ int sync_read(pm_ctx* c, double* host, const double* dev, int n) {
   return check_hip(c, e, "reading a reduction result");
 }
 
-int dtype_ok(int d) { return d == PM_FP32 || d == PM_FP64; }
+int dtype_ok(int d) { return d == PM_FP32 || d == PM_FP64; }  // caller-facing arrays
 
 // Checkpoint header: [tag of grid and dtype, step count, physics hash], then
 // the population region and the residual snapshot plane.
@@ -394,7 +400,7 @@ uint64_t physics_hash(const pm_ctx* c) {
   return h;
 }
 
-size_t snap_bytes(const pm_ctx* c) { return c->lay.plane * c->lay.elem; }
+size_t snap_bytes(const pm_ctx* c) { return c->lay.plane * c->lay.pelem; }
 
 int init_ctx(const pm_params* p, void* dev_ws, size_t ws_bytes, void* hip_stream, bool pair, pm_ctx** out);
 
@@ -485,6 +491,7 @@ int init_ctx(const pm_params* p, void* dev_ws, size_t ws_bytes, void* hip_stream
   (void)hipGetDevice(&c->device);
   c->k32 = kparams<float>(*p, L, dev_ws, lay);
   c->k64 = kparams<double>(*p, L, dev_ws, lay);
+  c->k16 = kparams<float, _Float16>(*p, L, dev_ws, lay);
   c->pair = pair;
   if (pair) {
     c->k32b = c->k32;
@@ -510,12 +517,12 @@ int init_ctx(const pm_params* p, void* dev_ws, size_t ws_bytes, void* hip_stream
   }
   const double dg_init = (1.0 / 6.0) * (p->T_init - 0.5);
   e = dispatch(c, [&](auto& kp) {
-    using T = typename std::remove_reference_t<decltype(*kp.f)>;
+    using T = typename std::remove_reference_t<decltype(kp)>::compute_t;
     return pm::launch_init(kp, c->launch, (T)dg_init, c->lay.pop_bytes);
   });
   if (e == hipSuccess)
     e = dispatch(c, [&](auto& kp) {
-      using T = typename std::remove_reference_t<decltype(*kp.f)>;
+      using T = typename std::remove_reference_t<decltype(kp)>::compute_t;
       T* snap = (T*)((char*)c->ws + c->lay.off_snap);
       return pm::launch_residual(kp, c->launch, 0, snap, c->red, c->red + pm::RED_BLOCKS, 1);
     });
@@ -546,7 +553,7 @@ int pm_set_logda(pm_ctx* c, const void* dev_plane, int dtype) {
   if (!c->p.has_logda) return ctx_fail(c, PM_ESTATE, "pm_set_logda: context created with has_logda = 0");
   if (!dev_plane || !dtype_ok(dtype)) return ctx_fail(c, PM_EINVAL, "pm_set_logda: bad plane or dtype");
   hipError_t e = dispatch(c, [&](auto& kp) {
-    using T = typename std::remove_reference_t<decltype(*kp.f)>;
+    using T = typename std::remove_reference_t<decltype(kp)>::compute_t;
     return pm::launch_set_logda(kp, c->launch, (T*)kp.logda, dev_plane, dtype == PM_FP64);
   });
   return check_hip(c, e, "pm_set_logda");
@@ -599,7 +606,7 @@ int pm_residual(pm_ctx* c, double* r_out, int64_t* at_step) {
   const int parity = (int)(c->steps & 1);
   double* dev = c->red + pm::RED_BLOCKS;
   hipError_t e = dispatch(c, [&](auto& kp) {
-    using T = typename std::remove_reference_t<decltype(*kp.f)>;
+    using T = typename std::remove_reference_t<decltype(kp)>::compute_t;
     T* snap = (T*)((char*)c->ws + c->lay.off_snap);
     return pm::launch_residual(kp, c->launch, parity, snap, c->red, dev, 0);
   });
@@ -814,6 +821,10 @@ int sweep_layout(const pm_params* cases, int n, SweepLayout& L, char* msg, size_
     }
     if (cases[i].has_logda) {
       snprintf(msg, len, "sweep: per-cell log-Da planes are not supported in a sweep");
+      return PM_EINVAL;
+    }
+    if (cases[i].dtype == PM_FP16) {
+      snprintf(msg, len, "sweep: FP16 storage is not supported in a sweep");
       return PM_EINVAL;
     }
     L.off[i] = o;
@@ -1258,6 +1269,10 @@ int adj_layout(const pm_params& p, int64_t T, int64_t C, AdjLayout& A, char* msg
     snprintf(msg, len, "adjoint: only PM_CLAMP_NU is supported");
     return PM_EINVAL;
   }
+  if (p.dtype == PM_FP16) {
+    snprintf(msg, len, "adjoint: FP16 storage is not supported (FP32 or FP64 forward states)");
+    return PM_EINVAL;
+  }
   if (p.gx != 0.0 || p.gy != 0.0) {
     snprintf(msg, len, "adjoint: extra body forces are not supported");
     return PM_EINVAL;
@@ -1564,8 +1579,9 @@ size_t pm_adjoint_vjp_scratch_bytes(const pm_ctx* c) {
 int pm_adjoint_vjp(pm_ctx* c, const void* lam_next, void* lam, void* grad_logda, void* dev_scratch,
                    size_t scratch_bytes, double* grad_scalars) {
   if (!c || !lam_next || !lam || !dev_scratch) return PM_EINVAL;
-  if (c->p.periodic_x || c->p.periodic_y || c->p.clamp_mode != PM_CLAMP_NU || c->p.gx != 0.0 || c->p.gy != 0.0)
-    return ctx_fail(c, PM_EINVAL, "pm_adjoint_vjp: cavity walls, PM_CLAMP_NU and no body force only");
+  if (c->p.periodic_x || c->p.periodic_y || c->p.clamp_mode != PM_CLAMP_NU || c->p.gx != 0.0 || c->p.gy != 0.0 ||
+      c->p.dtype == PM_FP16)
+    return ctx_fail(c, PM_EINVAL, "pm_adjoint_vjp: cavity walls, PM_CLAMP_NU, no body force, FP32/FP64 only");
   if (c->p.has_logda && !grad_logda) return ctx_fail(c, PM_EINVAL, "pm_adjoint_vjp: grad_logda needed");
   const size_t need = pm_adjoint_vjp_scratch_bytes(c);
   if (scratch_bytes < need) return ctx_fail(c, PM_ESTATE, "pm_adjoint_vjp: scratch < %zu bytes", need);
@@ -1634,8 +1650,10 @@ extern "C" {
 
 int pm_adjoint_vjp_noalloc(pm_ctx* c, const void* lam_next, void* lam, void* grad_logda, double* grad_scalars) {
   if (!c || !lam_next || !lam) return PM_EINVAL;
-  if (c->p.periodic_x || c->p.periodic_y || c->p.clamp_mode != PM_CLAMP_NU || c->p.gx != 0.0 || c->p.gy != 0.0)
-    return ctx_fail(c, PM_EINVAL, "pm_adjoint_vjp_noalloc: cavity walls, PM_CLAMP_NU and no body force only");
+  if (c->p.periodic_x || c->p.periodic_y || c->p.clamp_mode != PM_CLAMP_NU || c->p.gx != 0.0 || c->p.gy != 0.0 ||
+      c->p.dtype == PM_FP16)
+    return ctx_fail(c, PM_EINVAL,
+                    "pm_adjoint_vjp_noalloc: cavity walls, PM_CLAMP_NU, no body force, FP32/FP64 only");
   if (c->p.has_logda && !grad_logda) return ctx_fail(c, PM_EINVAL, "pm_adjoint_vjp_noalloc: grad_logda needed");
   const int nblocks = c->launch.ntiles;
   if (nblocks > NOALLOC_MAX_WG)

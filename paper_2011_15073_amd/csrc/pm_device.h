@@ -6,6 +6,7 @@
 #include "pm_internal.h"
 
 #include <cmath>
+#include <type_traits>
 
 namespace pm {
 namespace dev {
@@ -51,28 +52,33 @@ template <> __device__ __forceinline__ double flog2<double>(double x) { return l
 template <> __device__ __forceinline__ double fexp2<double>(double x) { return exp2(x); }
 template <> __device__ __forceinline__ double fsqrt<double>(double x) { return sqrt(x); }
 
-// Global loads and stores; NT = streaming (non-temporal) hint, used for the
-// aligned population accesses of the step (each value is touched once per
-// step, so keeping it in L2/MALL only evicts useful lines).
-template <typename T, bool NT>
-__device__ __forceinline__ T ldg(const T* a) {
-  if constexpr (NT) return __builtin_nontemporal_load(a);
-  else return *a;
+// Global loads and stores of stored populations (type S), converted from and
+// to the compute type T (a store to _Float16 rounds to nearest); NT =
+// streaming (non-temporal) hint, used for the aligned population accesses of
+// the step (each value is touched once per step, so keeping it in L2/MALL
+// only evicts useful lines).
+template <typename T, bool NT, typename S>
+__device__ __forceinline__ T ldg(const S* a) {
+  S v;
+  if constexpr (NT) v = __builtin_nontemporal_load(a);
+  else v = *a;
+  return (T)v;
 }
-template <typename T, bool NT>
-__device__ __forceinline__ void stg(T* a, T v) {
+template <typename T, bool NT, typename S>
+__device__ __forceinline__ void stg(S* a, T v) {
 #ifdef PM_EMULATE_FP32_STORAGE
   v = (T)(float)v;
 #endif
-  if constexpr (NT) __builtin_nontemporal_store(v, a);
-  else *a = v;
+  const S w = (S)v;
+  if constexpr (NT) __builtin_nontemporal_store(w, a);
+  else *a = w;
 }
 
 // ---- population addressing ----
 // Population q of node (i, j) lives at f[q * qs + j * rs + i] (g likewise);
 // see KParams.  pop_off gives the node part j * rs + i.
-template <typename T>
-__device__ __forceinline__ int64_t pop_off(const KParams<T>& p, int i, int j) {
+template <typename T, typename S>
+__device__ __forceinline__ int64_t pop_off(const KParams<T, S>& p, int i, int j) {
   return (int64_t)j * p.rs + i;
 }
 
@@ -106,41 +112,41 @@ __device__ __forceinline__ bool nbr(int nx, int ny, int px, int py, int i, int j
 }
 
 // o = pop_off(p, i, j) of the node itself.
-template <typename T, int Q>
-__device__ __forceinline__ T pull_f(const KParams<T>& p, int i, int j, int64_t o) {
+template <typename T, int Q, typename S>
+__device__ __forceinline__ T pull_f(const KParams<T, S>& p, int i, int j, int64_t o) {
   int si, sj;
   const bool in = nbr<Q>(p.nx, p.ny, p.px, p.py, i, j, -1, -1, si, sj);
-  const T* a = in ? (p.f + OPP[Q] * p.qs + pop_off(p, si, sj)) : (p.f + Q * p.qs + o);
+  const S* a = in ? (p.f + OPP[Q] * p.qs + pop_off(p, si, sj)) : (p.f + Q * p.qs + o);
   return ldg<T, EXv[Q] == 0>(a);
 }
 
-template <typename T, int Q>
-__device__ __forceinline__ void push_f(const KParams<T>& p, int i, int j, int64_t o, T v) {
+template <typename T, int Q, typename S>
+__device__ __forceinline__ void push_f(const KParams<T, S>& p, int i, int j, int64_t o, T v) {
   int di, dj;
   const bool in = nbr<Q>(p.nx, p.ny, p.px, p.py, i, j, 1, 1, di, dj);
-  T* a = in ? (p.f + Q * p.qs + pop_off(p, di, dj)) : (p.f + OPP[Q] * p.qs + o);
+  S* a = in ? (p.f + Q * p.qs + pop_off(p, di, dj)) : (p.f + OPP[Q] * p.qs + o);
   stg<T, EXv[Q] == 0>(a, v);
 }
 
 // Thermal pull: across x = 0 the incoming dg_1 is -dg*_3 + hotc (anti-bounce-
 // back, hot wall), across x = nx the incoming dg_3 is -dg*_1 + coldc (cold
 // wall), across y = 0, ny plain bounce-back (adiabatic).
-template <typename T, int Q>
-__device__ __forceinline__ T pull_g(const KParams<T>& p, int i, int j, int64_t o) {
+template <typename T, int Q, typename S>
+__device__ __forceinline__ T pull_g(const KParams<T, S>& p, int i, int j, int64_t o) {
   int si, sj;
   const bool in = nbr<Q>(p.nx, p.ny, p.px, p.py, i, j, -1, -1, si, sj);
-  const T* a = in ? (p.g + OPP[Q] * p.qs + pop_off(p, si, sj)) : (p.g + Q * p.qs + o);
+  const S* a = in ? (p.g + OPP[Q] * p.qs + pop_off(p, si, sj)) : (p.g + Q * p.qs + o);
   T v = ldg<T, EXv[Q] == 0>(a);
   if (EXv[Q] == 1) v = in ? v : p.hotc - v;
   if (EXv[Q] == -1) v = in ? v : p.coldc - v;
   return v;
 }
 
-template <typename T, int Q>
-__device__ __forceinline__ void push_g(const KParams<T>& p, int i, int j, int64_t o, T v) {
+template <typename T, int Q, typename S>
+__device__ __forceinline__ void push_g(const KParams<T, S>& p, int i, int j, int64_t o, T v) {
   int di, dj;
   const bool in = nbr<Q>(p.nx, p.ny, p.px, p.py, i, j, 1, 1, di, dj);
-  T* a = in ? (p.g + Q * p.qs + pop_off(p, di, dj)) : (p.g + OPP[Q] * p.qs + o);
+  S* a = in ? (p.g + Q * p.qs + pop_off(p, di, dj)) : (p.g + OPP[Q] * p.qs + o);
   T w = v;
   if (EXv[Q] == -1) w = in ? v : p.hotc - v;  // leaves through x = 0
   if (EXv[Q] == 1) w = in ? v : p.coldc - v;  // leaves through x = nx
@@ -150,61 +156,61 @@ __device__ __forceinline__ void push_g(const KParams<T>& p, int i, int j, int64_
 // Interior fast path of the odd step: every neighbour is inside the grid.
 // Rows j - 1, j, j + 1 are addressed from one wave-uniform base (row j - 1)
 // plus a non-negative 32-bit lane offset.
-template <typename T>
+template <typename S>
 struct RowBase {
-  T* f;  // p.f + (j - 1) rs
-  T* g;
+  S* f;  // p.f + (j - 1) rs
+  S* g;
 };
-template <typename T>
-__device__ __forceinline__ RowBase<T> row_base(const KParams<T>& p, int j) {
+template <typename T, typename S>
+__device__ __forceinline__ RowBase<S> row_base(const KParams<T, S>& p, int j) {
   const int64_t o = (int64_t)(j - 1) * p.rs;
-  return RowBase<T>{p.f + o, p.g + o};
+  return RowBase<S>{p.f + o, p.g + o};
 }
 // offset of population q of node (i + dx, j + dy) from row j - 1
-template <typename T>
-__device__ __forceinline__ unsigned in_off(const KParams<T>& p, int q, int i, int dx, int dy) {
+template <typename T, typename S>
+__device__ __forceinline__ unsigned in_off(const KParams<T, S>& p, int q, int i, int dx, int dy) {
   return (unsigned)(q * p.qs + (1 + dy) * p.rs + (i + dx));
 }
 
-template <typename T>
-__device__ __forceinline__ void load_interior_odd(const KParams<T>& p, const RowBase<T>& b, int i,
+template <typename T, typename S>
+__device__ __forceinline__ void load_interior_odd(const KParams<T, S>& p, const RowBase<S>& b, int i,
                                                   T df[9], T dg[5]) {
   df[0] = ldg<T, true>(b.f + in_off(p, 0, i, 0, 0));
 #pragma unroll
   for (int q = 1; q < 9; ++q) {
-    const T* a = b.f + in_off(p, OPP[q], i, -EXv[q], -EYv[q]);
+    const S* a = b.f + in_off(p, OPP[q], i, -EXv[q], -EYv[q]);
     df[q] = EXv[q] == 0 ? ldg<T, true>(a) : ldg<T, false>(a);
   }
   dg[0] = ldg<T, true>(b.g + in_off(p, 0, i, 0, 0));
 #pragma unroll
   for (int q = 1; q < 5; ++q) {
-    const T* a = b.g + in_off(p, OPP[q], i, -EXv[q], -EYv[q]);
+    const S* a = b.g + in_off(p, OPP[q], i, -EXv[q], -EYv[q]);
     dg[q] = EXv[q] == 0 ? ldg<T, true>(a) : ldg<T, false>(a);
   }
 }
 
-template <typename T>
-__device__ __forceinline__ void store_interior_odd(const KParams<T>& p, const RowBase<T>& b, int i,
+template <typename T, typename S>
+__device__ __forceinline__ void store_interior_odd(const KParams<T, S>& p, const RowBase<S>& b, int i,
                                                    const T df[9], const T dg[5]) {
   stg<T, true>(b.f + in_off(p, 0, i, 0, 0), df[0]);
 #pragma unroll
   for (int q = 1; q < 9; ++q) {
-    T* a = b.f + in_off(p, q, i, EXv[q], EYv[q]);
+    S* a = b.f + in_off(p, q, i, EXv[q], EYv[q]);
     if (EXv[q] == 0) stg<T, true>(a, df[q]);
     else stg<T, false>(a, df[q]);
   }
   stg<T, true>(b.g + in_off(p, 0, i, 0, 0), dg[0]);
 #pragma unroll
   for (int q = 1; q < 5; ++q) {
-    T* a = b.g + in_off(p, q, i, EXv[q], EYv[q]);
+    S* a = b.g + in_off(p, q, i, EXv[q], EYv[q]);
     if (EXv[q] == 0) stg<T, true>(a, dg[q]);
     else stg<T, false>(a, dg[q]);
   }
 }
 
 // Pre-collision populations of node (i, j) for a state of the given parity.
-template <typename T, bool ODD>
-__device__ __forceinline__ void load_node(const KParams<T>& p, int i, int j, T df[9], T dg[5]) {
+template <typename T, bool ODD, typename S>
+__device__ __forceinline__ void load_node(const KParams<T, S>& p, int i, int j, T df[9], T dg[5]) {
   const int64_t o = pop_off(p, i, j);
   if (!ODD) {
 #pragma unroll
@@ -229,14 +235,14 @@ __device__ __forceinline__ void load_node(const KParams<T>& p, int i, int j, T d
   }
 }
 
-template <typename T, bool ODD>
-__device__ __forceinline__ void load_g(const KParams<T>& p, int i, int j, T dg[5]) {
+template <typename T, bool ODD, typename S>
+__device__ __forceinline__ void load_g(const KParams<T, S>& p, int i, int j, T dg[5]) {
   const int64_t o = pop_off(p, i, j);
   if (!ODD) {
 #pragma unroll
-    for (int q = 0; q < 5; ++q) dg[q] = p.g[q * p.qs + o];
+    for (int q = 0; q < 5; ++q) dg[q] = (T)p.g[q * p.qs + o];
   } else {
-    dg[0] = p.g[o];
+    dg[0] = (T)p.g[o];
     dg[1] = pull_g<T, 1>(p, i, j, o);
     dg[2] = pull_g<T, 2>(p, i, j, o);
     dg[3] = pull_g<T, 3>(p, i, j, o);
@@ -244,8 +250,8 @@ __device__ __forceinline__ void load_g(const KParams<T>& p, int i, int j, T dg[5
   }
 }
 
-template <typename T, bool ODD>
-__device__ __forceinline__ void store_node(const KParams<T>& p, int i, int j, const T df[9],
+template <typename T, bool ODD, typename S>
+__device__ __forceinline__ void store_node(const KParams<T, S>& p, int i, int j, const T df[9],
                                            const T dg[5]) {
   const int64_t o = pop_off(p, i, j);
   if (!ODD) {
@@ -289,32 +295,31 @@ __device__ __forceinline__ void store_node(const KParams<T>& p, int i, int j, co
 // two instead of four or five.
 constexpr int NU_FP32_STEPS = 4;
 
-template <typename T>
-__device__ __forceinline__ T nu_start(const KParams<T>& p, T A, T B) {
-  const T y = (p.lc0 + p.nm1 * (T(0.5) * flog2<T>(B) - T(1.584962500721156181453738943947816508))) * p.inv_n;
-  return fmin(fmax(y, p.y_lo), p.y_hi);  // log2(B = 0) = -inf: lands on a bound
-}
-
-template <>
-__device__ __forceinline__ double nu_start<double>(const KParams<double>& p, double A, double B) {
-  const float lo = (float)p.y_lo, hi = (float)p.y_hi, lc0 = (float)p.lc0, nm1 = (float)p.nm1;
-  const float Af = (float)A, Bf = (float)B;
-  float y = (lc0 + nm1 * (0.5f * __builtin_amdgcn_logf(Bf) - 1.5849625007f)) * (float)p.inv_n;
-  y = fminf(fmaxf(y, lo), hi);
-  for (int it = 0; it < NU_FP32_STEPS; ++it) {  // a fixed count: no lane depends on another
-    const float nu = __builtin_amdgcn_exp2f(y);
-    const float s = __builtin_amdgcn_rcpf(3.0f * nu + 0.5f);
-    const float g2 = Af + Bf * s * s;
-    const float G = (y - lc0) - 0.5f * nm1 * __builtin_amdgcn_logf(g2);
-    const float dG = 1.0f + 3.0f * nm1 * Bf * s * s * s * nu * __builtin_amdgcn_rcpf(g2);
-    const float yn = y - G * __builtin_amdgcn_rcpf(dG);
-    if (g2 > 0.0f && yn == yn) y = fminf(fmaxf(yn, lo), hi);  // no shear in FP32: the FP64 steps decide
+template <typename T, typename S>
+__device__ __forceinline__ T nu_start(const KParams<T, S>& p, T A, T B) {
+  if constexpr (std::is_same<T, double>::value) {
+    const float lo = (float)p.y_lo, hi = (float)p.y_hi, lc0 = (float)p.lc0, nm1 = (float)p.nm1;
+    const float Af = (float)A, Bf = (float)B;
+    float y = (lc0 + nm1 * (0.5f * __builtin_amdgcn_logf(Bf) - 1.5849625007f)) * (float)p.inv_n;
+    y = fminf(fmaxf(y, lo), hi);
+    for (int it = 0; it < NU_FP32_STEPS; ++it) {  // a fixed count: no lane depends on another
+      const float nu = __builtin_amdgcn_exp2f(y);
+      const float s = __builtin_amdgcn_rcpf(3.0f * nu + 0.5f);
+      const float g2 = Af + Bf * s * s;
+      const float G = (y - lc0) - 0.5f * nm1 * __builtin_amdgcn_logf(g2);
+      const float dG = 1.0f + 3.0f * nm1 * Bf * s * s * s * nu * __builtin_amdgcn_rcpf(g2);
+      const float yn = y - G * __builtin_amdgcn_rcpf(dG);
+      if (g2 > 0.0f && yn == yn) y = fminf(fmaxf(yn, lo), hi);  // no shear in FP32: the FP64 steps decide
+    }
+    return fmin(fmax((double)y, p.y_lo), p.y_hi);
+  } else {
+    const T y = (p.lc0 + p.nm1 * (T(0.5) * flog2<T>(B) - T(1.584962500721156181453738943947816508))) * p.inv_n;
+    return fmin(fmax(y, p.y_lo), p.y_hi);  // log2(B = 0) = -inf: lands on a bound
   }
-  return fmin(fmax((double)y, p.y_lo), p.y_hi);
 }
 
-template <typename T>
-__device__ __forceinline__ T solve_nu(const KParams<T>& p, T A, T B) {
+template <typename T, typename S>
+__device__ __forceinline__ T solve_nu(const KParams<T, S>& p, T A, T B) {
   const T half = T(0.5);
   const T hn = half * p.nm1;
   T y = nu_start<T>(p, A, B);
@@ -348,8 +353,8 @@ struct Macro {
 
 // Steps 2-6 of the update for one node (shifted populations in registers):
 // moments, buoyancy, provisional velocity, viscosity, porous velocity.
-template <typename T, bool POW, bool LOGDA>
-__device__ __forceinline__ void node_macros(const KParams<T>& p, int k, const T df[9],
+template <typename T, bool POW, bool LOGDA, typename S>
+__device__ __forceinline__ void node_macros(const KParams<T, S>& p, int k, const T df[9],
                                             const T dg[5], T& drho, T& rho, T& jx, T& jy,
                                             T& dT, T& Gx, T& Gy, T& nu, T& ux, T& uy, T& invK,
                                             T& invsK, T& m1, T& m7, T& m8) {
@@ -380,7 +385,7 @@ __device__ __forceinline__ void node_macros(const KParams<T>& p, int k, const T 
     const T irho2 = irho * irho;
     const T A = T(0.25) * p.s_e * p.s_e * en * en * irho2;
     const T B = T(2.25) * (pn * pn + T(4) * qn * qn) * irho2;
-    nu = solve_nu<T>(p, A, B);
+    nu = solve_nu(p, A, B);
   } else {
     nu = p.nu_newt;
   }
@@ -401,16 +406,20 @@ __device__ __forceinline__ void node_macros(const KParams<T>& p, int k, const T 
   uy = vy * iden;
 }
 
-// ---- stochastic rounding of the FP32 population updates (PM_ROUND_STOCHASTIC) ----
+// ---- stochastic rounding of the population updates (PM_ROUND_STOCHASTIC) ----
 // With round-to-nearest, a state near a steady flow rounds the same way step
 // after step, and the slowly decaying modes of the cavity accumulate that
 // fixed rounding pattern into a bias far above one rounding.  The update is
 // therefore written as f* = a + b (a the stored population, b its change from
 // the moment changes) and added as a + (b + xi), xi uniform on
-// (-ulp(a), ulp(a)), then rounded to nearest.  A uniform dither whose width is
-// a whole number of grid spacings leaves rounding to nearest unbiased, and
-// 2 ulp(a) is one, two or four spacings at a + b (a + b one binade above a,
-// in a's binade, or one below).  One uniform per node update serves all 14
+// (-ulp(a), ulp(a)) with ulp the spacing of the storage type S at a, then
+// rounded to nearest in S (FP32: by the FP32 add; _Float16: by the store,
+// the FP32 sum being far finer than the half spacing).  A uniform dither whose
+// width is a whole number of grid spacings leaves rounding to nearest
+// unbiased, and 2 ulp(a) is one, two or four spacings at a + b (a + b one
+// binade above a, in a's binade, or one below; below the smallest normal half
+// the spacing is constant and the dither two spacings wide).  One uniform per
+// node update serves all 14
 // populations (each is still rounded without bias); it has 24 bits and comes
 // from one round of the "lowbias32" integer hash (Chris Wellons, hash
 // prospector, public domain) of the node index and three of the node's
@@ -425,25 +434,34 @@ __device__ __forceinline__ unsigned mix32(unsigned x) {
   return x;
 }
 
-// The node's dither scale: u 2^-22 with u uniform on (-1/2, 1/2), so that
-// us * 2^e(a) = u * 2 ulp(a).
+// Storage precision: mantissa bits of S (FP32 23, _Float16 10).
+template <typename S>
+constexpr int mant_bits() { return std::is_same<S, _Float16>::value ? 10 : 23; }
+
+// The node's dither scale: u 2^-(m-1) with u uniform on (-1/2, 1/2) and m the
+// mantissa bits of S, so that us * 2^e(a) = u * 2 ulp_S(a).
+template <typename S>
 __device__ __forceinline__ float dither_scale(int k, float a0, float a1, float a2) {
   const unsigned h = mix32((unsigned)k * 0x9e3779b1u ^ __float_as_uint(a0) ^
                            __builtin_amdgcn_alignbit(__float_as_uint(a1), __float_as_uint(a1), 11) ^
                            __builtin_amdgcn_alignbit(__float_as_uint(a2), __float_as_uint(a2), 22));
-  return __builtin_fmaf((float)(h >> 8), 0x1p-46f, (0x1p-25f - 0.5f) * 0x1p-22f);
+  constexpr float sc = 1.0f / (float)(1u << (mant_bits<S>() - 1));
+  return __builtin_fmaf((float)(h >> 8), 0x1p-24f * sc, (0x1p-25f - 0.5f) * sc);
 }
 
-// a + b rounded with the node's dither (2^e(a) is 0 for a zero or subnormal a:
-// no dither there).
+// a + b with the node's dither, before the rounding to S.  FP32: 2^e(a) is 0
+// for a zero or subnormal a (no dither there).  _Float16: 2^e(a) is floored
+// at the smallest normal half, 2^-14, whose ulp is the subnormal spacing.
+template <typename S>
 __device__ __forceinline__ float dither_add(float a, float b, float us) {
-  const float p2 = __uint_as_float(__float_as_uint(a) & 0x7f800000u);
-  return a + __builtin_fmaf(us, p2, b);
+  unsigned e = __float_as_uint(a) & 0x7f800000u;
+  if constexpr (std::is_same<S, _Float16>::value) e = max(e, 0x38800000u);  // the bits of 2^-14
+  return a + __builtin_fmaf(us, __uint_as_float(e), b);
 }
 
 // The full local update: Steps 2-9 on shifted populations, in place.
-template <typename T, bool POW, bool LOGDA, bool SR = false>
-__device__ __forceinline__ void collide(const KParams<T>& p, int k, T df[9], T dg[5]) {
+template <typename T, bool POW, bool LOGDA, bool SR = false, typename S>
+__device__ __forceinline__ void collide(const KParams<T, S>& p, int k, T df[9], T dg[5]) {
   T drho, rho, jx, jy, dT, Gx, Gy, nu, ux, uy, invK, invsK, m1, m7, m8;
   node_macros<T, POW, LOGDA>(p, k, df, dg, drho, rho, jx, jy, dT, Gx, Gy, nu, ux, uy, invK,
                              invsK, m1, m7, m8);
@@ -486,8 +504,8 @@ __device__ __forceinline__ void collide(const KParams<T>& p, int k, T df[9], T d
   const T x5 = a3 + a4, y5 = a5 + a6;
   float us = 0.0f;  // the node's dither scale (SR)
   if constexpr (SR) {
-    static_assert(sizeof(T) == 4, "stochastic rounding is for FP32 storage");
-    us = dither_scale(k, df[0], dg[0], df[5]);
+    static_assert(sizeof(T) == 4, "stochastic rounding is for FP32 compute (FP32 or FP16 storage)");
+    us = dither_scale<S>(k, df[0], dg[0], df[5]);
     // the same back-transform applied to the moment changes ms - m (the
     // density is conserved), added to the incoming populations
     const T d1 = (ms1 - m1) * T(1.0 / 36.0), d2 = (ms2 - m2) * T(1.0 / 36.0);
@@ -497,15 +515,15 @@ __device__ __forceinline__ void collide(const KParams<T>& p, int k, T df[9], T d
     const T e14 = -d1 - T(2) * d2, e58 = T(2) * d1 + d2;
     const T u1 = d3 - T(2) * d4, v1 = d5 - T(2) * d6;
     const T u5 = d3 + d4, v5 = d5 + d6;
-    df[0] = dither_add(df[0], T(4) * (d2 - d1), us);
-    df[1] = dither_add(df[1], (e14 + u1) + d7, us);
-    df[2] = dither_add(df[2], (e14 + v1) - d7, us);
-    df[3] = dither_add(df[3], (e14 - u1) + d7, us);
-    df[4] = dither_add(df[4], (e14 - v1) - d7, us);
-    df[5] = dither_add(df[5], (e58 + u5) + (v5 + d8), us);
-    df[6] = dither_add(df[6], (e58 - u5) + (v5 - d8), us);
-    df[7] = dither_add(df[7], (e58 - u5) - (v5 - d8), us);
-    df[8] = dither_add(df[8], (e58 + u5) - (v5 + d8), us);
+    df[0] = dither_add<S>(df[0], T(4) * (d2 - d1), us);
+    df[1] = dither_add<S>(df[1], (e14 + u1) + d7, us);
+    df[2] = dither_add<S>(df[2], (e14 + v1) - d7, us);
+    df[3] = dither_add<S>(df[3], (e14 - u1) + d7, us);
+    df[4] = dither_add<S>(df[4], (e14 - v1) - d7, us);
+    df[5] = dither_add<S>(df[5], (e58 + u5) + (v5 + d8), us);
+    df[6] = dither_add<S>(df[6], (e58 - u5) + (v5 - d8), us);
+    df[7] = dither_add<S>(df[7], (e58 - u5) - (v5 - d8), us);
+    df[8] = dither_add<S>(df[8], (e58 + u5) - (v5 + d8), us);
   } else {
     df[0] = (a0 - T(4) * a1) + T(4) * a2;
     df[1] = (b14 + x1) + a7;
@@ -529,11 +547,11 @@ __device__ __forceinline__ void collide(const KParams<T>& p, int k, T df[9], T d
   if constexpr (SR) {
     const T e1 = (ns1 - n1) * T(0.5), e2 = (ns2 - n2) * T(0.5);
     const T e3 = (ns3 - n3) * T(0.05), e4 = (ns4 - n4) * T(0.25);  // T is conserved
-    dg[0] = dither_add(dg[0], T(-4) * e3, us);
-    dg[1] = dither_add(dg[1], (e3 + e1) + e4, us);
-    dg[2] = dither_add(dg[2], (e3 + e2) - e4, us);
-    dg[3] = dither_add(dg[3], (e3 - e1) + e4, us);
-    dg[4] = dither_add(dg[4], (e3 - e2) - e4, us);
+    dg[0] = dither_add<S>(dg[0], T(-4) * e3, us);
+    dg[1] = dither_add<S>(dg[1], (e3 + e1) + e4, us);
+    dg[2] = dither_add<S>(dg[2], (e3 + e2) - e4, us);
+    dg[3] = dither_add<S>(dg[3], (e3 - e1) + e4, us);
+    dg[4] = dither_add<S>(dg[4], (e3 - e2) - e4, us);
   } else {
     const T c0 = dT * T(0.2), c1 = ns1 * T(0.5), c2 = ns2 * T(0.5);
     const T c3 = ns3 * T(0.05), c4 = ns4 * T(0.25);
@@ -550,8 +568,8 @@ __device__ __forceinline__ void collide(const KParams<T>& p, int k, T df[9], T d
 // scatter into the state d (d == p: the in-place AA update; d != p: the same
 // update written to another buffer, which then holds the complete next
 // state because every slot is written exactly once per step).
-template <typename T, bool ODD, bool POW, bool LOGDA, bool SR = false>
-__device__ __forceinline__ void step_tile(const KParams<T>& p, const KParams<T>& d, int i0, int j, int lx) {
+template <typename T, bool ODD, bool POW, bool LOGDA, bool SR = false, typename S>
+__device__ __forceinline__ void step_tile(const KParams<T, S>& p, const KParams<T, S>& d, int i0, int j, int lx) {
   const int i = i0 + lx;
   T df[9], dg[5];
   if (ODD) {

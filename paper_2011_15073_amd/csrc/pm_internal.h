@@ -9,18 +9,21 @@
 
 namespace pm {
 
-// Everything one node update needs, already converted to the compute type.
+// Everything one node update needs, already converted to the compute type T;
+// the populations are stored as S (T itself, or _Float16 with FP32 compute).
 // Populations are stored shifted: df_q = f_q - w_q and dg_q = g_q - w_q T_ref
-// (T_ref = 1/2), which keeps FP32 resolution on the small deviations from the
-// rest state.  Population q of node (i, j) is f[q * qs + j * rs + i] (g
-// likewise).  The library lays the 14 populations of a row out one after the
-// other (row-interleaved: qs = padded nx, rs = 14 qs, g = f + 9 qs); the
-// per-cell planes (log10 Da, the residual snapshot) and every caller-facing
-// field use the natural index k = j * nx + i.
-template <typename T>
+// (T_ref = 1/2), which keeps the storage precision on the small deviations
+// from the rest state.  Population q of node (i, j) is f[q * qs + j * rs + i]
+// (g likewise).  The library lays the 14 populations of a row out one after
+// the other (row-interleaved: qs = padded nx, rs = 14 qs, g = f + 9 qs); the
+// per-cell planes (log10 Da, the residual snapshot, both of type T) and every
+// caller-facing field use the natural index k = j * nx + i.
+template <typename T, typename S = T>
 struct KParams {
-  T* f;            // 9 populations
-  T* g;            // 5 populations
+  using compute_t = T;
+  using storage_t = S;
+  S* f;            // 9 populations
+  S* g;            // 5 populations
   const T* logda;  // per-cell log10(Da) plane [ny][nx] or nullptr
   int64_t qs;      // population stride in elements
   int64_t rs;      // row stride in elements
@@ -34,7 +37,7 @@ struct KParams {
   T nm1, inv_n;    // n - 1, 1 / n
   T tol;           // Newton tolerance on log2(nu)
   int max_it;
-  int sr;          // 1: round the FP32 population updates stochastically (PM_ROUND_STOCHASTIC)
+  int sr;          // 1: round the population updates stochastically (FP32 or FP16 storage)
   // porous medium
   T eps, inv_eps, invK, invsK, Feps, inv_Kscale;
   // body forces: G = (gx, gy + gbeta (T - T_m))
@@ -114,29 +117,29 @@ constexpr int RED_BLOCKS = 1024; // partial-result slots of the residual
 constexpr int GRID_Y_MAX = 65535; // largest gridDim.y of any launch: taller grids loop over rows
 
 // parity 0: state in natural layout; 1: after an odd number of steps
-template <typename T>
-hipError_t launch_step(const KParams<T>& p, const Launch& L, int parity, bool pow, bool logda);
+template <typename T, typename S>
+hipError_t launch_step(const KParams<T, S>& p, const Launch& L, int parity, bool pow, bool logda);
 template <typename T>
 hipError_t launch_step_oop(const KParams<T>& src, const KParams<T>& dst, const Launch& L, int parity,
                            bool pow, bool logda);
-template <typename T>
-hipError_t launch_init(const KParams<T>& p, const Launch& L, T dg_init, size_t pop_bytes);
-template <typename T>
-hipError_t launch_nu(const KParams<T>& p, const Launch& L, int parity, double* out);
-template <typename T>
-hipError_t launch_residual(const KParams<T>& p, const Launch& L, int parity, T* snap,
+template <typename T, typename S>
+hipError_t launch_init(const KParams<T, S>& p, const Launch& L, T dg_init, size_t pop_bytes);
+template <typename T, typename S>
+hipError_t launch_nu(const KParams<T, S>& p, const Launch& L, int parity, double* out);
+template <typename T, typename S>
+hipError_t launch_residual(const KParams<T, S>& p, const Launch& L, int parity, T* snap,
                            double* partial, double* out, int take_snapshot_only);
-template <typename T>
-hipError_t launch_fields(const KParams<T>& p, const Launch& L, int parity, bool pow, bool logda,
+template <typename T, typename S>
+hipError_t launch_fields(const KParams<T, S>& p, const Launch& L, int parity, bool pow, bool logda,
                          void* U, void* V, void* th, void* nu, int out_fp64);
-template <typename T>
-hipError_t launch_get_pop(const KParams<T>& p, const Launch& L, int parity, void* f, void* g,
+template <typename T, typename S>
+hipError_t launch_get_pop(const KParams<T, S>& p, const Launch& L, int parity, void* f, void* g,
                           int out_fp64);
-template <typename T>
-hipError_t launch_set_pop(const KParams<T>& p, const Launch& L, const void* f, const void* g,
+template <typename T, typename S>
+hipError_t launch_set_pop(const KParams<T, S>& p, const Launch& L, const void* f, const void* g,
                           int in_fp64);
-template <typename T>
-hipError_t launch_set_logda(const KParams<T>& p, const Launch& L, T* dst, const void* src,
+template <typename T, typename S>
+hipError_t launch_set_logda(const KParams<T, S>& p, const Launch& L, T* dst, const void* src,
                             int in_fp64);
 // Sweep tiles are tw columns by th rows: tw in {64, 128, 256}, th in {1, 2, 4},
 // tw * th <= TILE threads (a wave then lies within one grid row).  any_sr:

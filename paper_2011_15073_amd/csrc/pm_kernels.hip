@@ -38,8 +38,8 @@ namespace {
 using namespace pm::dev;
 
 // One workgroup per row segment of blockDim.x nodes (64, 128 or 256).
-template <typename T, bool ODD, bool POW, bool LOGDA, bool SR>
-__global__ __launch_bounds__(TILE) void k_step(KParams<T> p, int tiles_x, int ntiles) {
+template <typename T, bool ODD, bool POW, bool LOGDA, bool SR, typename S>
+__global__ __launch_bounds__(TILE) void k_step(KParams<T, S> p, int tiles_x, int ntiles) {
   const int tile = tile_of_block(blockIdx.x, ntiles);
   const int j = tile / tiles_x;
   step_tile<T, ODD, POW, LOGDA, SR>(p, p, (tile - j * tiles_x) * (int)blockDim.x, j, threadIdx.x);
@@ -205,24 +205,24 @@ __global__ __launch_bounds__(TILE) void k_step_multi(const SweepCase<T>* __restr
 
 // Rest state: df = 0, dg_q = w_q (T_init - T_ref).  (The padding of the
 // population region is cleared by the launcher.)
-template <typename T>
-__global__ void k_init(KParams<T> p, T dg_init) {
+template <typename T, typename S>
+__global__ void k_init(KParams<T, S> p, T dg_init) {
   const int64_t n = (int64_t)p.nx * p.ny;
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
        k += (int64_t)gridDim.x * blockDim.x) {
     const int j = (int)(k / p.nx), i = (int)(k - (int64_t)j * p.nx);
     const int64_t o = pop_off(p, i, j);
 #pragma unroll
-    for (int q = 0; q < 9; ++q) p.f[q * p.qs + o] = T(0);
-    p.g[o] = dg_init * T(2);  // w_0 = 1/3 = 2 w_1
+    for (int q = 0; q < 9; ++q) p.f[q * p.qs + o] = S(0);
+    p.g[o] = (S)(dg_init * T(2));  // w_0 = 1/3 = 2 w_1
 #pragma unroll
-    for (int q = 1; q < 5; ++q) p.g[q * p.qs + o] = dg_init;
+    for (int q = 1; q < 5; ++q) p.g[q * p.qs + o] = (S)dg_init;
   }
 }
 
 // Eq. (24): one workgroup, fixed summation order (deterministic).
-template <typename T>
-__global__ __launch_bounds__(256) void k_nu(KParams<T> p, int parity, double* out) {
+template <typename T, typename S>
+__global__ __launch_bounds__(256) void k_nu(KParams<T, S> p, int parity, double* out) {
   __shared__ double red[256];
   double acc = 0.0;
   for (int j = threadIdx.x; j < p.ny; j += 256) {
@@ -248,8 +248,8 @@ __global__ __launch_bounds__(256) void k_nu(KParams<T> p, int parity, double* ou
 }
 
 // Residual: per-block max |theta - snapshot|, snapshot := theta.
-template <typename T>
-__global__ __launch_bounds__(256) void k_resid(KParams<T> p, int parity, T* snap,
+template <typename T, typename S>
+__global__ __launch_bounds__(256) void k_resid(KParams<T, S> p, int parity, T* snap,
                                                double* partial, int snapshot_only) {
   __shared__ double red[256];
   double mx = 0.0;
@@ -353,8 +353,8 @@ __global__ void k_retire(const SweepCase<T>* __restrict__ cases, int ncases,
   }
 }
 
-template <typename T, bool ODD, bool POW, bool LOGDA, typename O>
-__global__ __launch_bounds__(TILE) void k_fields(KParams<T> p, O* U, O* V, O* th, O* nuo) {
+template <typename T, bool ODD, bool POW, bool LOGDA, typename O, typename S>
+__global__ __launch_bounds__(TILE) void k_fields(KParams<T, S> p, O* U, O* V, O* th, O* nuo) {
   const int i = blockIdx.x * TILE + threadIdx.x;
   if (i >= p.nx) return;
   for (int j = blockIdx.y; j < p.ny; j += gridDim.y) {
@@ -381,8 +381,8 @@ __device__ __forceinline__ T w5(int q) {
   return q == 0 ? T(1.0 / 3.0) : T(1.0 / 6.0);
 }
 
-template <typename T, bool ODD, typename O>
-__global__ __launch_bounds__(TILE) void k_get_pop(KParams<T> p, O* f, O* g) {
+template <typename T, bool ODD, typename O, typename S>
+__global__ __launch_bounds__(TILE) void k_get_pop(KParams<T, S> p, O* f, O* g) {
   const int i = blockIdx.x * TILE + threadIdx.x;
   if (i >= p.nx) return;
   const int64_t n = (int64_t)p.nx * p.ny;
@@ -397,18 +397,18 @@ __global__ __launch_bounds__(TILE) void k_get_pop(KParams<T> p, O* f, O* g) {
   }
 }
 
-template <typename T, typename I>
-__global__ __launch_bounds__(TILE) void k_set_pop(KParams<T> p, const I* f, const I* g) {
+template <typename T, typename I, typename S>
+__global__ __launch_bounds__(TILE) void k_set_pop(KParams<T, S> p, const I* f, const I* g) {
   const int i = blockIdx.x * TILE + threadIdx.x;
   if (i >= p.nx) return;
   const int64_t n = (int64_t)p.nx * p.ny;
   for (int j = blockIdx.y; j < p.ny; j += gridDim.y) {
     const int64_t k = (int64_t)j * p.nx + i, o = pop_off(p, i, j);
 #pragma unroll
-    for (int q = 0; q < 9; ++q) p.f[q * p.qs + o] = (T)((double)f[q * n + k] - (double)w9<T>(q));
+    for (int q = 0; q < 9; ++q) p.f[q * p.qs + o] = (S)((double)f[q * n + k] - (double)w9<T>(q));
 #pragma unroll
     for (int q = 0; q < 5; ++q)
-      p.g[q * p.qs + o] = (T)((double)g[q * n + k] - (double)w5<T>(q) * (double)p.T_ref);
+      p.g[q * p.qs + o] = (S)((double)g[q * n + k] - (double)w5<T>(q) * (double)p.T_ref);
   }
 }
 
@@ -508,12 +508,12 @@ inline int grid_for(int64_t n, int per = 256, int cap = 65536) {
 
 }  // namespace
 
-template <typename T>
-hipError_t launch_step(const KParams<T>& p, const Launch& L, int parity, bool pow, bool logda) {
+template <typename T, typename S>
+hipError_t launch_step(const KParams<T, S>& p, const Launch& L, int parity, bool pow, bool logda) {
   if (!(L.step_w == 64 || L.step_w == 128 || L.step_w == 256) || L.step_w > TILE) return hipErrorInvalidValue;
   dim3 grid(L.step_ntiles), block(L.step_w);
 #define PM_STEP(ODD, POW, LOG, SR) \
-  hipLaunchKernelGGL((k_step<T, ODD, POW, LOG, SR>), grid, block, 0, L.stream, p, L.step_tiles_x, L.step_ntiles)
+  hipLaunchKernelGGL((k_step<T, ODD, POW, LOG, SR, S>), grid, block, 0, L.stream, p, L.step_tiles_x, L.step_ntiles)
 #define PM_STEP_ALL(SR)                                                                             \
   if (parity) {                                                                                     \
     if (pow) { if (logda) PM_STEP(true, true, true, SR); else PM_STEP(true, true, false, SR); }       \
@@ -613,38 +613,38 @@ hipError_t launch_resid_multi(const SweepCase<T>* cases, int ncases, const int2*
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_init(const KParams<T>& p, const Launch& L, T dg_init, size_t pop_bytes) {
+template <typename T, typename S>
+hipError_t launch_init(const KParams<T, S>& p, const Launch& L, T dg_init, size_t pop_bytes) {
   // whole population region first (row padding included), then the nodes
   hipError_t e = hipMemsetAsync(p.f, 0, pop_bytes, L.stream);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_init<T>), dim3(grid_for((int64_t)p.nx * p.ny)), dim3(256), 0, L.stream,
+  hipLaunchKernelGGL((k_init<T, S>), dim3(grid_for((int64_t)p.nx * p.ny)), dim3(256), 0, L.stream,
                      p, dg_init);
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_nu(const KParams<T>& p, const Launch& L, int parity, double* out) {
-  hipLaunchKernelGGL((k_nu<T>), dim3(1), dim3(256), 0, L.stream, p, parity, out);
+template <typename T, typename S>
+hipError_t launch_nu(const KParams<T, S>& p, const Launch& L, int parity, double* out) {
+  hipLaunchKernelGGL((k_nu<T, S>), dim3(1), dim3(256), 0, L.stream, p, parity, out);
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_residual(const KParams<T>& p, const Launch& L, int parity, T* snap,
+template <typename T, typename S>
+hipError_t launch_residual(const KParams<T, S>& p, const Launch& L, int parity, T* snap,
                            double* partial, double* out, int snapshot_only) {
   const int nb = grid_for((int64_t)p.nx * p.ny, 256, RED_BLOCKS);
-  hipLaunchKernelGGL((k_resid<T>), dim3(nb), dim3(256), 0, L.stream, p, parity, snap, partial,
+  hipLaunchKernelGGL((k_resid<T, S>), dim3(nb), dim3(256), 0, L.stream, p, parity, snap, partial,
                      snapshot_only);
   hipLaunchKernelGGL(k_max_final, dim3(1), dim3(256), 0, L.stream, (const double*)partial, nb, out);
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_fields(const KParams<T>& p, const Launch& L, int parity, bool pow, bool logda,
+template <typename T, typename S>
+hipError_t launch_fields(const KParams<T, S>& p, const Launch& L, int parity, bool pow, bool logda,
                          void* U, void* V, void* th, void* nu, int out_fp64) {
   dim3 grid(L.tiles_x, std::min(p.ny, GRID_Y_MAX)), block(TILE);
 #define PM_F(ODD, POW, LOG, O)                                                              \
-  hipLaunchKernelGGL((k_fields<T, ODD, POW, LOG, O>), grid, block, 0, L.stream, p, (O*)U, \
+  hipLaunchKernelGGL((k_fields<T, ODD, POW, LOG, O, S>), grid, block, 0, L.stream, p, (O*)U, \
                      (O*)V, (O*)th, (O*)nu)
 #define PM_F2(ODD, POW, LOG) \
   do { if (out_fp64) PM_F(ODD, POW, LOG, double); else PM_F(ODD, POW, LOG, float); } while (0)
@@ -659,33 +659,33 @@ hipError_t launch_fields(const KParams<T>& p, const Launch& L, int parity, bool 
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_get_pop(const KParams<T>& p, const Launch& L, int parity, void* f, void* g,
+template <typename T, typename S>
+hipError_t launch_get_pop(const KParams<T, S>& p, const Launch& L, int parity, void* f, void* g,
                           int out_fp64) {
   dim3 grid(L.tiles_x, std::min(p.ny, GRID_Y_MAX)), block(TILE);
   if (parity) {
-    if (out_fp64) hipLaunchKernelGGL((k_get_pop<T, true, double>), grid, block, 0, L.stream, p, (double*)f, (double*)g);
-    else hipLaunchKernelGGL((k_get_pop<T, true, float>), grid, block, 0, L.stream, p, (float*)f, (float*)g);
+    if (out_fp64) hipLaunchKernelGGL((k_get_pop<T, true, double, S>), grid, block, 0, L.stream, p, (double*)f, (double*)g);
+    else hipLaunchKernelGGL((k_get_pop<T, true, float, S>), grid, block, 0, L.stream, p, (float*)f, (float*)g);
   } else {
-    if (out_fp64) hipLaunchKernelGGL((k_get_pop<T, false, double>), grid, block, 0, L.stream, p, (double*)f, (double*)g);
-    else hipLaunchKernelGGL((k_get_pop<T, false, float>), grid, block, 0, L.stream, p, (float*)f, (float*)g);
+    if (out_fp64) hipLaunchKernelGGL((k_get_pop<T, false, double, S>), grid, block, 0, L.stream, p, (double*)f, (double*)g);
+    else hipLaunchKernelGGL((k_get_pop<T, false, float, S>), grid, block, 0, L.stream, p, (float*)f, (float*)g);
   }
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_set_pop(const KParams<T>& p, const Launch& L, const void* f, const void* g,
+template <typename T, typename S>
+hipError_t launch_set_pop(const KParams<T, S>& p, const Launch& L, const void* f, const void* g,
                           int in_fp64) {
   dim3 grid(L.tiles_x, std::min(p.ny, GRID_Y_MAX)), block(TILE);
   if (in_fp64)
-    hipLaunchKernelGGL((k_set_pop<T, double>), grid, block, 0, L.stream, p, (const double*)f, (const double*)g);
+    hipLaunchKernelGGL((k_set_pop<T, double, S>), grid, block, 0, L.stream, p, (const double*)f, (const double*)g);
   else
-    hipLaunchKernelGGL((k_set_pop<T, float>), grid, block, 0, L.stream, p, (const float*)f, (const float*)g);
+    hipLaunchKernelGGL((k_set_pop<T, float, S>), grid, block, 0, L.stream, p, (const float*)f, (const float*)g);
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_set_logda(const KParams<T>& p, const Launch& L, T* dst, const void* src,
+template <typename T, typename S>
+hipError_t launch_set_logda(const KParams<T, S>& p, const Launch& L, T* dst, const void* src,
                             int in_fp64) {
   const int64_t n = (int64_t)p.nx * p.ny;
   if (in_fp64)
@@ -732,20 +732,23 @@ hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, hipStream
   return hipGetLastError();
 }
 
+#define PM_INST_S(T, S)                                                                          \
+  template hipError_t launch_step<T, S>(const KParams<T, S>&, const Launch&, int, bool, bool);    \
+  template hipError_t launch_init<T, S>(const KParams<T, S>&, const Launch&, T, size_t);          \
+  template hipError_t launch_nu<T, S>(const KParams<T, S>&, const Launch&, int, double*);         \
+  template hipError_t launch_residual<T, S>(const KParams<T, S>&, const Launch&, int, T*, double*, \
+                                            double*, int);                                         \
+  template hipError_t launch_fields<T, S>(const KParams<T, S>&, const Launch&, int, bool, bool,   \
+                                          void*, void*, void*, void*, int);                        \
+  template hipError_t launch_get_pop<T, S>(const KParams<T, S>&, const Launch&, int, void*, void*, \
+                                           int);                                                   \
+  template hipError_t launch_set_pop<T, S>(const KParams<T, S>&, const Launch&, const void*,      \
+                                           const void*, int);                                      \
+  template hipError_t launch_set_logda<T, S>(const KParams<T, S>&, const Launch&, T*, const void*, int);
 #define PM_INST(T)                                                                              \
-  template hipError_t launch_step<T>(const KParams<T>&, const Launch&, int, bool, bool);        \
+  PM_INST_S(T, T)                                                                               \
   template hipError_t launch_step_oop<T>(const KParams<T>&, const KParams<T>&, const Launch&, int, \
                                          bool, bool);                                           \
-  template hipError_t launch_init<T>(const KParams<T>&, const Launch&, T, size_t);              \
-  template hipError_t launch_nu<T>(const KParams<T>&, const Launch&, int, double*);             \
-  template hipError_t launch_residual<T>(const KParams<T>&, const Launch&, int, T*, double*,    \
-                                         double*, int);                                         \
-  template hipError_t launch_fields<T>(const KParams<T>&, const Launch&, int, bool, bool, void*, \
-                                       void*, void*, void*, int);                               \
-  template hipError_t launch_get_pop<T>(const KParams<T>&, const Launch&, int, void*, void*, int); \
-  template hipError_t launch_set_pop<T>(const KParams<T>&, const Launch&, const void*,          \
-                                        const void*, int);                                      \
-  template hipError_t launch_set_logda<T>(const KParams<T>&, const Launch&, T*, const void*, int); \
   template hipError_t launch_step_multi<T>(const SweepCase<T>*, const int2*, const int*, int, int, \
                                            int, int, bool, hipStream_t);                          \
   template hipError_t launch_resid_multi<T>(const SweepCase<T>*, int, const int2*, int*, int, int, \
@@ -753,6 +756,8 @@ hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, hipStream
                                             int64_t, hipStream_t);
 PM_INST(float)
 PM_INST(double)
+PM_INST_S(float, _Float16)
 #undef PM_INST
+#undef PM_INST_S
 
 }  // namespace pm

@@ -165,6 +165,24 @@ def test_adjoint_workspace_checks():
     assert ws(p, 100, 10)[1] < ws(p, 100, 1)[1]  # 100 checkpoints against 10
     for T, Cc in ((0, 1), (10, 0), (10, 11)):
         assert ws(p, T, Cc)[0] == _lib.PM_EINVAL
-    for bad in (dict(periodic_x=1), dict(clamp_mode=1), dict(gx=1e-6)):
+    for bad in (dict(periodic_x=1), dict(clamp_mode=1), dict(gx=1e-6), dict(dtype="fp16")):
         assert ws(P.make_params(48, 40, **dict(kw, **bad)), 100, 10)[0] == _lib.PM_EINVAL
     assert _lib.lib.pm_last_error(None).decode()
+
+
+def test_fp16_storage_parameters():
+    """PM_FP16: half the population bytes of FP32, FP32 per-cell planes, the
+    single-step kernel only (PM_STEP_PAIR refused, PM_STEP_AUTO takes no second
+    region), stochastic or nearest rounding, not in a sweep."""
+    kw = dict(n=0.8, Da=1e-2, Ra=1e5, Pr=10.0, eps=0.6)
+    n = 4096 * 4096
+    f16 = P.workspace_bytes(P.make_params(4096, dtype="fp16", **kw))
+    f32 = P.workspace_bytes(P.make_params(4096, dtype="fp32", step_kernel="single", **kw))
+    assert 14 * n * 2 <= f16 < f32 and f32 - f16 >= 14 * n * 2
+    assert P.workspace_bytes(P.make_params(4096, dtype="fp16", step_kernel="single", **kw)) == f16
+    with pytest.raises(P.PmError):
+        P.workspace_bytes(P.make_params(4096, dtype="fp16", step_kernel="pair", **kw))
+    for r in ("auto", "stochastic", "nearest"):
+        P.lattice_of(P.make_params(64, dtype="fp16", rounding=r, **kw))
+    assert _sweep_ws([P.make_params(64, dtype="fp16", **kw)])[0] == _lib.PM_EINVAL
+    assert "FP16" in _lib.lib.pm_last_error(None).decode()

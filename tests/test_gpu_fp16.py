@@ -1,0 +1,120 @@
+"""GPU: 16-bit population storage (PM_FP16: IEEE half shifted populations,
+FP32 arithmetic, stochastically rounded stores) against the FP64 oracle.
+
+Bars, from the measured loss of half-precision storage (a half ulp is 2^-11
+relative, against 2^-24 for FP32):
+  * one step from a random non-equilibrium state: every stored population
+    within two half ulps (2^-9 relative) of the oracle's step from the same
+    half-rounded state -- the stochastic rounding adds at most one ulp of
+    dither and half an ulp of rounding;
+  * 64^2 cavities after 20 000 steps from rest (measured: Newtonian fields
+    1.7e-3, Nu 7.3e-3; power law at Ra = 1e5 fields 5.6e-3, Nu 3.3e-3): fields
+    within 3e-3 (Newtonian) and 1e-2 (power law), Nu within 1.5e-2 and 1e-2.
+    Nu is limited by noise: Eq. (24) weighs the two wall columns' theta by
+    N (8 - 9 theta_0 + theta_1) / 3, so the rounding noise of the stored
+    thermal populations, about 1e-4 in theta, reaches Nu amplified about
+    twenty times at Nu ~ 1.  Round-to-nearest half storage is 20 to 70 times
+    worse (it accumulates its fixed rounding pattern in the slow modes).
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_2011_15073_amd as P
+from paper_2011_15073_amd import inputs
+from pairs import compare_fields, compare_nu, gpu_for, oracle_for
+
+pytestmark = pytest.mark.gpu
+
+W9 = inputs.W9
+W5 = inputs.W5
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+@pytest.mark.parametrize("kw", [dict(n=0.7, Da=1e-2, Ra=1e4, Pr=10.0, eps=0.6),
+                                dict(n=1.0, Da=0.1, Ra=1e3, Pr=10.0, eps=0.6)], ids=["n0.7", "n1.0"])
+@pytest.mark.parametrize("pre", [0, 1])
+def test_fp16_step_within_two_half_ulps(kw, pre):
+    nx, ny = 70, 19
+    f0, g0 = inputs.random_state(nx, ny, seed=13, amp=0.03, amp_T=0.2)
+    cav = gpu_for(nx, ny, dtype="fp16", **kw)
+    cav.set_populations(torch.from_numpy(f0), torch.from_numpy(g0))
+    cav.step(pre)
+    fh, gh = (t.cpu().numpy() for t in cav.populations(torch.float64))  # the stored (half) state
+    orc = oracle_for(nx, ny, **kw)
+    orc.set_state(fh, gh)
+    orc.step(1)
+    fr, gr = orc.state()
+    cav.step(1)
+    fg, gg = (t.cpu().numpy() for t in cav.populations(torch.float64))
+    worst = 0.0
+    for got, ref, inp, w in ((fg, fr, fh, W9), (gg, gr, gh, W5 * 0.5)):
+        for q in range(got.shape[0]):
+            d_ref, d_in = ref[q] - w[q], inp[q] - w[q]   # the shifted values the kernels store
+            scale = max(2.0 ** -14, np.abs(d_ref).max(), np.abs(d_in).max())
+            err = np.abs(got[q] - ref[q]).max()
+            worst = max(worst, err / (2.0 ** -9 * scale))
+            assert err <= 2.0 ** -9 * scale, (q, err, scale)
+    log(f"fp16 one step {kw} pre={pre}: worst error {worst:.3f} of the two-half-ulp bound")
+
+
+CFG0 = dict(n=1.0, Da=0.1, Ra=1e3, Pr=10.0, eps=0.6)
+PLAW = dict(n=0.8, Da=1e-2, Ra=1e5, Pr=10.0, eps=0.6)
+
+
+@pytest.mark.parametrize("kw,bar,bar_nu", [(CFG0, 3e-3, 1.5e-2), (PLAW, 1e-2, 1e-2)],
+                         ids=["newtonian", "power-law"])
+def test_fp16_cavity_64_20000_steps(kw, bar, bar_nu):
+    orc = oracle_for(64, **kw).step(20000)
+    out = {}
+    for rounding in ("auto", "nearest"):
+        cav = gpu_for(64, dtype="fp16", rounding=rounding, **kw)
+        cav.step(20000)
+        errs = compare_fields(cav, orc)
+        out[rounding] = (max(errs.values()), compare_nu(cav, orc))
+        log(f"fp16 ({rounding}) 64^2 {kw}: {errs}, |dNu|/Nu {out[rounding][1]:.3e}")
+    assert out["auto"][0] <= bar and out["auto"][1] <= bar_nu
+    assert out["nearest"][0] > 3 * out["auto"][0]
+
+
+def test_fp16_state_round_trip_and_checkpoint():
+    kw = dict(PLAW)
+    a = gpu_for(48, 40, dtype="fp16", **kw)
+    a.step(301)
+    snap = a.save_state()
+    f1, g1 = a.populations(torch.float32)
+    a.step(200)
+    b = gpu_for(48, 40, dtype="fp16", **kw)
+    b.load_state(snap)
+    fb, gb = b.populations(torch.float32)
+    assert torch.equal(f1, fb) and torch.equal(g1, gb)
+    b.step(200)
+    fa, ga = a.populations(torch.float32)
+    fb, gb = b.populations(torch.float32)
+    assert torch.equal(fa, fb) and torch.equal(ga, gb) and a.nu() == b.nu()
+    # an FP32 context of the same grid refuses the FP16 state (another dtype)
+    c = gpu_for(48, 40, dtype="fp32", **kw)
+    with pytest.raises(P.PmError):
+        c.load_state(snap)
+    # get -> set returns the same stored (half) populations, read back exactly in FP64
+    # (at an even step count: after an odd one the populations that crossed a
+    # thermal wall carry the anti-bounce-back constant, which is not a half)
+    a.step(1)
+    fa64, ga64 = a.populations(torch.float64)
+    c16 = gpu_for(48, 40, dtype="fp16", **kw)
+    c16.set_populations(fa64, ga64)
+    fc, gc = c16.populations(torch.float64)
+    assert torch.equal(fa64, fc) and torch.equal(ga64, gc)
+
+
+def test_fp16_is_refused_where_unsupported():
+    with pytest.raises(P.PmError, match="FP16"):
+        P.Sweep([dict(nx=32, dtype="fp16", **CFG0)])
+    cav = gpu_for(32, dtype="fp16", logda=torch.from_numpy(inputs.logda_field(32, seed=1)), **CFG0)
+    with pytest.raises(P.PmError, match="FP16"):
+        P.Adjoint(cav, 10)
+    with pytest.raises(P.PmError, match="single|FP32"):
+        gpu_for(4096, dtype="fp16", step_kernel="pair", **CFG0)
