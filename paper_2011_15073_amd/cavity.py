@@ -97,7 +97,23 @@ class Cavity:
         self._check(lib.pm_residual(self._h, C.byref(v), C.byref(at)))
         return (v.value, at.value) if with_step else v.value
 
-    def run_to_steady(self, tol=1e-8, check_every=1000, max_steps=10_000_000):
+    def run_to_steady(self, tol=1e-8, check_every=1000, max_steps=10_000_000, history=None):
+        """Advance until the residual taken every check_every steps is below
+        tol, or max_steps steps; returns (last residual, steps taken).  With
+        ``history`` (a list), the same chunks and stopping rule are driven
+        from here and (step count, residual, Nu) is appended after every
+        check: the residual and Nu histories of the run."""
+        if history is not None and check_every > 0 and max_steps >= 0:
+            done, r = 0, float("inf")
+            while done < max_steps:
+                k = min(int(check_every), int(max_steps) - done)
+                self.step(k)
+                done += k
+                r, at = self.residual(with_step=True)
+                history.append((at, r, self.nu()))
+                if r < tol:
+                    break
+            return r, done
         steps, r = C.c_int64(), C.c_double()
         self._check(lib.pm_run_to_steady(self._h, float(tol), int(check_every), int(max_steps),
                                          C.byref(steps), C.byref(r)))

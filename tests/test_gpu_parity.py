@@ -322,6 +322,32 @@ def test_checkpoint_keeps_the_residual_snapshot():
     assert (ra, sa) == (rb, sb) and sa == 2000
 
 
+@pytest.mark.parametrize("max_steps", [6000, 6500, 40_000])
+def test_run_to_steady_history_follows_the_library_loop(max_steps):
+    """run_to_steady with a history list drives the same chunks and stopping
+    rule as pm_run_to_steady (a cap that is not a multiple of the chunk, a
+    cap that is reached, a run that settles): same steps, same residual,
+    bitwise the same state; the history holds every check's step count,
+    residual and Nu, the last being the run's own."""
+    kw = dict(n=0.8, Da=1e-2, Ra=1e4, Pr=10.0, eps=0.6)
+    tol, check = 1e-7, 1000
+    a = gpu_for(40, dtype="fp64", **kw)
+    ra, sa = a.run_to_steady(tol=tol, check_every=check, max_steps=max_steps)
+    b = gpu_for(40, dtype="fp64", **kw)
+    hist = []
+    rb, sb = b.run_to_steady(tol=tol, check_every=check, max_steps=max_steps, history=hist)
+    log(f"cap {max_steps}: {sa} steps, r {ra:.3e}; history {[(s, f'{r:.2e}') for s, r, _ in hist]}")
+    assert (ra, sa) == (rb, sb)
+    assert [s for s, _, _ in hist] == [min(check * (i + 1), max_steps) for i in range(len(hist))]
+    assert hist[-1][0] == sb and hist[-1][1] == rb and hist[-1][2] == b.nu() == a.nu()
+    assert all(r >= tol for _, r, _ in hist[:-1])
+    fa, ga = a.populations()
+    fb, gb = b.populations()
+    assert torch.equal(fa, fb) and torch.equal(ga, gb)
+    if max_steps == 40_000:
+        assert rb < tol and sb < max_steps
+
+
 def test_runs_are_deterministic():
     kw = dict(n=0.6, Da=1e-3, Ra=1e5, Pr=10.0, eps=0.6)
     outs = []
