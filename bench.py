@@ -28,6 +28,7 @@ the FP64 CPU oracle timed on a bounded sample of the same workload on this
 host (all cores and one core).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-extras]
+       python bench.py --sweep | --adjoint | --paper-tables | --stream-function | --oracle-table
 """
 import argparse
 import hashlib
@@ -196,6 +197,72 @@ def cpu_baseline(budget_s=15.0, one_core=True):
             out["value_1core"] = None
             out["sample_1core"] = f"not measured: {type(e).__name__}"
     return out
+
+
+# The oracle's rate on each parity workload: (name, side, physics, log-Da
+# field?, steps of the whole run, sampled steps on all cores, sampled steps on
+# one core).  The steady-state run's 331 000 steps are the oracle's own stop
+# (max|dT| over 1000 steps < 1e-8, tests/golden/cfg1_256_oracle.npz); the
+# 27 sweep cases are sampled one after another and reported at 5000 steps each.
+ORACLE_WORKLOADS = [
+    ("64x64 Newtonian cavity, n=1 Da=0.1 Ra=1e3, 20000 steps", 64,
+     dict(n=1.0, Da=0.1, Ra=1e3, Pr=10.0, eps=0.6), False, 20000, 20000, 2000),
+    ("256x256 power-law cavity to steady state, n=0.6 Da=1e-3 Ra=1e5, 331000 steps", 256,
+     dict(n=0.6, Da=1e-3, Ra=1e5, Pr=10.0, eps=0.6), False, 331000, 1000, 100),
+    ("27 sweep cases (sides 128-512), 5000 steps each", None, None, False, 5000, 60, 6),
+    ("256x256 gradient workload forward, n=0.7 Ra=1e4, log10 Da ~ U[-3,-1], 5000 steps", 256,
+     dict(n=0.7, Ra=1e4, Pr=10.0, eps=0.6), True, 5000, 500, 50),
+]
+
+
+def _oracle_rates(one_core):
+    """Oracle MLUPS on each of ORACLE_WORKLOADS (sampled steps after one
+    warm-up step per grid)."""
+    import oracle as O
+    from paper_2011_15073_amd import inputs
+    out = []
+    for name, side, phys, logda, full, s_all, s_one in ORACLE_WORKLOADS:
+        k = s_one if one_core else s_all
+        if side is None:
+            runs = [(c["N"], dict(n=c["n"], Da=c["Da"], Ra=c["Ra"], Pr=10.0, eps=0.6), None)
+                    for c in inputs.sweep_cases(0)]
+        else:
+            runs = [(side, phys, inputs.logda_field(side, seed=0) if logda else None)]
+        upd, dt = 0, 0.0
+        for nx, ph, ld in runs:
+            orc = O.Oracle.from_physics(O.physics(nx, **ph), logda=ld)
+            orc.step(1)
+            t0 = time.perf_counter()
+            orc.step(k)
+            dt += time.perf_counter() - t0
+            upd += nx * nx * k
+        m = upd / dt / 1e6
+        out.append(dict(workload=name, steps_sampled=k, seconds=round(dt, 2), mlups=round(m, 3),
+                        est_full_run_s=round(upd / k * full / (m * 1e6), 1)))
+    return out
+
+
+def oracle_table_main(args):
+    """The FP64 oracle's throughput on the parity workloads, on all the
+    host's cores and on one core (a child process), with the wall time a
+    whole run would take at that rate."""
+    import subprocess
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+    log(f"oracle table: {threads} threads")
+    rows = _oracle_rates(one_core=False)
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    code = ("import sys, json; sys.path.insert(0, %r); import bench; "
+            "print(json.dumps(bench._oracle_rates(True)))" % ROOT)
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                       timeout=600, check=True)
+    one = json.loads(r.stdout.strip().splitlines()[-1])
+    for a, b in zip(rows, one):
+        a["cores"] = threads
+        a.update({k + "_1core": b[k] for k in ("steps_sampled", "seconds", "mlups", "est_full_run_s")})
+        log(f"oracle table: {a['workload']}: {a['mlups']} MLUPS on {threads} threads, "
+            f"{a['mlups_1core']} on one core")
+    print(json.dumps({"metric": "oracle MLUPS", "unit": "MLUPS", "kind": "oracle", "dtype": "f64",
+                      "cpu_model": cpu_model(), "cores": threads, "workloads": rows}), flush=True)
 
 
 def sweep_main(args):
@@ -437,6 +504,8 @@ def main():
                     help="time the stream function of the 4096^2 workload")
     ap.add_argument("--adjoint", action="store_true",
                     help="time the gradient of Nu (forward with checkpoints vs backward)")
+    ap.add_argument("--oracle-table", action="store_true",
+                    help="time the FP64 CPU oracle on the parity workloads (all cores and one core); no GPU")
     ap.add_argument("--adjoint-steps", type=int, default=5000)
     ap.add_argument("--adjoint-shear-floor", type=float, default=0.1,
                     help="nondimensional shear floor of the regularised adjoint (0: exact)")
@@ -447,6 +516,9 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.oracle_table:
+        oracle_table_main(args)
+        return
     if args.sweep:
         sweep_main(args)
         return

@@ -62,3 +62,16 @@ def test_kernel_hash_follows_code_not_comments(kind, tmp_path, monkeypatch):
     assert bench.kernel_hash(kind) == h0
     dev.write_text(text.replace("T(0.5)", "T(0.25)", 1))
     assert bench.kernel_hash(kind) != h0
+
+
+def test_oracle_table_rates(monkeypatch):
+    """The oracle-timing table (bench.py --oracle-table) on one-step samples:
+    every workload timed, its whole-run estimate the sampled rate scaled to
+    the run's node updates."""
+    small = [w[:5] + (1, 1) for w in bench.ORACLE_WORKLOADS if w[1] is not None]
+    monkeypatch.setattr(bench, "ORACLE_WORKLOADS", small)
+    rows = bench._oracle_rates(one_core=True)
+    assert len(rows) == len(small) == 3
+    for (name, side, _, _, full, _, _), r in zip(small, rows):
+        assert r["workload"] == name and r["steps_sampled"] == 1 and r["mlups"] > 0
+        assert r["est_full_run_s"] == pytest.approx(side * side * full / (r["mlups"] * 1e6), rel=2e-2, abs=0.2)
