@@ -126,17 +126,22 @@ __global__ __launch_bounds__(TILE) void k_step2(KParams<float> src, KParams<floa
   Still r1m{}, r10{}, r1p{};  // f* of rows a - 2, a - 1, a (this column)
   Still r2m{}, r20{}, r2p{};  // f** of rows a - 3, a - 2, a - 1
   int s1 = 0;                 // slot of row a; rows a - 1, a - 2 in s1 - 1, s1 - 2 (mod 3)
+  // S_k of the row A gathers next, loaded one row ahead: the loads of row
+  // a + 1 are issued once row a has been collided, and are in flight while
+  // rows a - 1 and a - 2 are finished (src is only read by this kernel).
+  float nf[9] = {}, ng[5] = {};
+  if (col && y0 - 2 >= 0) load_node<float, false>(src, c, y0 - 2, nf, ng);
   for (int a = y0 - 2; a <= y_end + 1; ++a, s1 = s1 == 2 ? 0 : s1 + 1) {
     const int s1m = s1 == 0 ? 2 : s1 - 1, s1mm = s1m == 0 ? 2 : s1m - 1;
     // A: step k at row a
     {
-      float df[9], dg[5];
       Still st{};
       if (col && a >= 0 && a < src.ny) {
-        load_node<float, false>(src, c, a, df, dg);
-        collide<float, POW, LOGDA, SR>(src, a * src.nx + c, df, dg);
-        put_row(ring1, s1, t, df, dg, st);
+        collide<float, POW, LOGDA, SR>(src, a * src.nx + c, nf, ng);
+        put_row(ring1, s1, t, nf, ng, st);
       }
+      if (col && a + 1 >= 0 && a + 1 < src.ny && a + 1 <= y_end + 1)
+        load_node<float, false>(src, c, a + 1, nf, ng);
       r1m = r10;
       r10 = r1p;
       r1p = st;
