@@ -552,9 +552,9 @@ def main():
     # storage) per node
     alg_launch = bpn * S * S
     achieved = alg_launch / launch_s / 1e9
-    alg_equiv = bpn * S * S * spl / launch_s / 1e9  # the method's 112 B per node update
+    alg_equiv = bpn * S * S * spl / launch_s / 1e9  # the method's bytes per node update (112 B in FP32)
     log(f"bench: {K['name'].split()[0]} {launch_s * 1e6:.1f} us/launch, {achieved:.0f} GB/s kernel-algorithmic, "
-        f"{alg_equiv:.0f} GB/s at 112 B per node update")
+        f"{alg_equiv:.0f} GB/s at {bpn} B per node update")
     copy_gbs = copy_ceiling(P, dev)
     log(f"bench: copy ceiling {copy_gbs:.0f} GB/s")
 

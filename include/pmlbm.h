@@ -95,8 +95,8 @@ typedef struct {
                           computes in FP32 and rounds every stored update stochastically (unless
                           rounding = PM_ROUND_NEAREST); the per-cell planes stay FP32.  It runs the
                           single-step kernel only, and neither sweeps nor the adjoint take it.
-                          Its fields are about 1e-3 of the FP64 oracle's after 20 000 steps of the
-                          64^2 cavities, against about 1e-6 for FP32. */
+                          Its fields are 1e-3 to 1e-2 of the FP64 oracle's after 20 000 steps of
+                          the 64^2 cavities, against about 1e-6 for FP32. */
   int32_t forchheimer; /* 1 (default): Ergun F_eps; 0: Darcy-Brinkman only */
   int32_t has_logda;   /* 1: per-cell log10(Da) plane from pm_set_logda */
   double s_e, s_eps, s_q; /* D2Q9 rates s1, s2, s4 = s6 (default 1.4, 1.4, 1.2) */
@@ -110,14 +110,17 @@ typedef struct {
                              a periodic axis or ny > 24 * 65535 is PM_EINVAL (PM_STEP_AUTO
                              then takes the single-step kernel). */
   int32_t rounding;       /* PM_ROUND_AUTO (default), PM_ROUND_NEAREST or PM_ROUND_STOCHASTIC (FP32
-                             only; PM_EINVAL with FP64).  Near a steady flow, round-to-nearest FP32
-                             storage makes the same rounding every step, and the cavity's slowly
-                             decaying modes turn that fixed pattern into a bias (about 5e-4 of the
-                             fields at the 256^2 power-law steady state).  Stochastic rounding adds
-                             each node's update to its stored populations with a uniform dither of
-                             width 2 ulp of the stored value, one 24-bit uniform per node update
-                             from a hash of the node and its inputs: deterministic, the same in
-                             every kernel, unbiased; about 3% more time per step at 4096^2. */
+                             and FP16 storage; PM_EINVAL with FP64).  Near a steady flow,
+                             round-to-nearest FP32 storage makes the same rounding every step, and
+                             the cavity's slowly decaying modes turn that fixed pattern into a bias
+                             (about 5e-4 of the fields at the 256^2 power-law steady state).
+                             Stochastic rounding draws one 32-bit word per node update from a hash
+                             of the node and its inputs (deterministic, the same in every kernel).
+                             FP32: each update is added to its stored population with a uniform
+                             dither of width 2 ulp of the stored value, then rounded to nearest.
+                             FP16: each update is converted by the hardware's stochastically
+                             rounding FP32 -> FP16 conversion, fed the word rotated per
+                             population.  Unbiased; no measurable cost per step at 4096^2. */
 } pm_params;
 
 /* Lattice values derived from pm_params (read-only description). */

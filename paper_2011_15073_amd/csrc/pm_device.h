@@ -64,14 +64,36 @@ __device__ __forceinline__ T ldg(const S* a) {
   else v = *a;
   return (T)v;
 }
-template <typename T, bool NT, typename S>
-__device__ __forceinline__ void stg(S* a, T v) {
+// Store v as S.  HSR (FP32 value, half storage): the conversion rounds
+// stochastically with the hardware's FP32 -> FP16 conversion, r the random
+// word (its high bits decide; every r rounds to one of the two halves that
+// bracket v, and a uniformly random r rounds without bias).
+template <typename T, bool NT, bool HSR = false, typename S>
+__device__ __forceinline__ void stg(S* a, T v, unsigned r = 0) {
 #ifdef PM_EMULATE_FP32_STORAGE
   v = (T)(float)v;
 #endif
-  const S w = (S)v;
+  S w;
+  if constexpr (HSR) {
+    static_assert(std::is_same<S, _Float16>::value && std::is_same<T, float>::value,
+                  "hardware stochastic rounding: FP32 values into half storage");
+    typedef short short2_t __attribute__((ext_vector_type(2)));
+    const short2_t h = __builtin_amdgcn_cvt_sr_f16_f32(short2_t{0, 0}, v, r, false);
+    w = __builtin_bit_cast(_Float16, (short)h.x);
+  } else {
+    w = (S)v;
+  }
   if constexpr (NT) __builtin_nontemporal_store(w, a);
   else *a = w;
+}
+
+// The stochastic conversion of population q (f0..f8, g0..g4 as q = 0..13)
+// takes the node's word rotated by SR_ROT[q] bits, so that the populations'
+// rounding decisions are not all taken at the same threshold (opposite
+// directions sit 14-16 bits apart).
+constexpr int SR_ROT[14] = {0, 2, 4, 16, 18, 6, 8, 20, 22, 10, 12, 14, 26, 24};
+__device__ __forceinline__ unsigned rot_word(unsigned r, int q) {
+  return SR_ROT[q] ? __builtin_amdgcn_alignbit(r, r, SR_ROT[q]) : r;
 }
 
 // ---- population addressing ----
@@ -120,12 +142,12 @@ __device__ __forceinline__ T pull_f(const KParams<T, S>& p, int i, int j, int64_
   return ldg<T, EXv[Q] == 0>(a);
 }
 
-template <typename T, int Q, typename S>
-__device__ __forceinline__ void push_f(const KParams<T, S>& p, int i, int j, int64_t o, T v) {
+template <typename T, int Q, bool HSR = false, typename S>
+__device__ __forceinline__ void push_f(const KParams<T, S>& p, int i, int j, int64_t o, T v, unsigned r = 0) {
   int di, dj;
   const bool in = nbr<Q>(p.nx, p.ny, p.px, p.py, i, j, 1, 1, di, dj);
   S* a = in ? (p.f + Q * p.qs + pop_off(p, di, dj)) : (p.f + OPP[Q] * p.qs + o);
-  stg<T, EXv[Q] == 0>(a, v);
+  stg<T, EXv[Q] == 0, HSR>(a, v, r);
 }
 
 // Thermal pull: across x = 0 the incoming dg_1 is -dg*_3 + hotc (anti-bounce-
@@ -142,15 +164,15 @@ __device__ __forceinline__ T pull_g(const KParams<T, S>& p, int i, int j, int64_
   return v;
 }
 
-template <typename T, int Q, typename S>
-__device__ __forceinline__ void push_g(const KParams<T, S>& p, int i, int j, int64_t o, T v) {
+template <typename T, int Q, bool HSR = false, typename S>
+__device__ __forceinline__ void push_g(const KParams<T, S>& p, int i, int j, int64_t o, T v, unsigned r = 0) {
   int di, dj;
   const bool in = nbr<Q>(p.nx, p.ny, p.px, p.py, i, j, 1, 1, di, dj);
   S* a = in ? (p.g + Q * p.qs + pop_off(p, di, dj)) : (p.g + OPP[Q] * p.qs + o);
   T w = v;
   if (EXv[Q] == -1) w = in ? v : p.hotc - v;  // leaves through x = 0
   if (EXv[Q] == 1) w = in ? v : p.coldc - v;  // leaves through x = nx
-  stg<T, EXv[Q] == 0>(a, w);
+  stg<T, EXv[Q] == 0, HSR>(a, w, r);
 }
 
 // Interior fast path of the odd step: every neighbour is inside the grid.
@@ -189,22 +211,22 @@ __device__ __forceinline__ void load_interior_odd(const KParams<T, S>& p, const 
   }
 }
 
-template <typename T, typename S>
+template <typename T, bool HSR = false, typename S>
 __device__ __forceinline__ void store_interior_odd(const KParams<T, S>& p, const RowBase<S>& b, int i,
-                                                   const T df[9], const T dg[5]) {
-  stg<T, true>(b.f + in_off(p, 0, i, 0, 0), df[0]);
+                                                   const T df[9], const T dg[5], unsigned r = 0) {
+  stg<T, true, HSR>(b.f + in_off(p, 0, i, 0, 0), df[0], r);
 #pragma unroll
   for (int q = 1; q < 9; ++q) {
     S* a = b.f + in_off(p, q, i, EXv[q], EYv[q]);
-    if (EXv[q] == 0) stg<T, true>(a, df[q]);
-    else stg<T, false>(a, df[q]);
+    if (EXv[q] == 0) stg<T, true, HSR>(a, df[q], rot_word(r, q));
+    else stg<T, false, HSR>(a, df[q], rot_word(r, q));
   }
-  stg<T, true>(b.g + in_off(p, 0, i, 0, 0), dg[0]);
+  stg<T, true, HSR>(b.g + in_off(p, 0, i, 0, 0), dg[0], rot_word(r, 9));
 #pragma unroll
   for (int q = 1; q < 5; ++q) {
     S* a = b.g + in_off(p, q, i, EXv[q], EYv[q]);
-    if (EXv[q] == 0) stg<T, true>(a, dg[q]);
-    else stg<T, false>(a, dg[q]);
+    if (EXv[q] == 0) stg<T, true, HSR>(a, dg[q], rot_word(r, 9 + q));
+    else stg<T, false, HSR>(a, dg[q], rot_word(r, 9 + q));
   }
 }
 
@@ -250,30 +272,30 @@ __device__ __forceinline__ void load_g(const KParams<T, S>& p, int i, int j, T d
   }
 }
 
-template <typename T, bool ODD, typename S>
+template <typename T, bool ODD, bool HSR = false, typename S>
 __device__ __forceinline__ void store_node(const KParams<T, S>& p, int i, int j, const T df[9],
-                                           const T dg[5]) {
+                                           const T dg[5], unsigned r = 0) {
   const int64_t o = pop_off(p, i, j);
   if (!ODD) {
 #pragma unroll
-    for (int q = 0; q < 9; ++q) stg<T, true>(p.f + OPP[q] * p.qs + o, df[q]);
+    for (int q = 0; q < 9; ++q) stg<T, true, HSR>(p.f + OPP[q] * p.qs + o, df[q], rot_word(r, q));
 #pragma unroll
-    for (int q = 0; q < 5; ++q) stg<T, true>(p.g + OPP[q] * p.qs + o, dg[q]);
+    for (int q = 0; q < 5; ++q) stg<T, true, HSR>(p.g + OPP[q] * p.qs + o, dg[q], rot_word(r, 9 + q));
   } else {
-    stg<T, true>(p.f + o, df[0]);
-    push_f<T, 1>(p, i, j, o, df[1]);
-    push_f<T, 2>(p, i, j, o, df[2]);
-    push_f<T, 3>(p, i, j, o, df[3]);
-    push_f<T, 4>(p, i, j, o, df[4]);
-    push_f<T, 5>(p, i, j, o, df[5]);
-    push_f<T, 6>(p, i, j, o, df[6]);
-    push_f<T, 7>(p, i, j, o, df[7]);
-    push_f<T, 8>(p, i, j, o, df[8]);
-    stg<T, true>(p.g + o, dg[0]);
-    push_g<T, 1>(p, i, j, o, dg[1]);
-    push_g<T, 2>(p, i, j, o, dg[2]);
-    push_g<T, 3>(p, i, j, o, dg[3]);
-    push_g<T, 4>(p, i, j, o, dg[4]);
+    stg<T, true, HSR>(p.f + o, df[0], r);
+    push_f<T, 1, HSR>(p, i, j, o, df[1], rot_word(r, 1));
+    push_f<T, 2, HSR>(p, i, j, o, df[2], rot_word(r, 2));
+    push_f<T, 3, HSR>(p, i, j, o, df[3], rot_word(r, 3));
+    push_f<T, 4, HSR>(p, i, j, o, df[4], rot_word(r, 4));
+    push_f<T, 5, HSR>(p, i, j, o, df[5], rot_word(r, 5));
+    push_f<T, 6, HSR>(p, i, j, o, df[6], rot_word(r, 6));
+    push_f<T, 7, HSR>(p, i, j, o, df[7], rot_word(r, 7));
+    push_f<T, 8, HSR>(p, i, j, o, df[8], rot_word(r, 8));
+    stg<T, true, HSR>(p.g + o, dg[0], rot_word(r, 9));
+    push_g<T, 1, HSR>(p, i, j, o, dg[1], rot_word(r, 10));
+    push_g<T, 2, HSR>(p, i, j, o, dg[2], rot_word(r, 11));
+    push_g<T, 3, HSR>(p, i, j, o, dg[3], rot_word(r, 12));
+    push_g<T, 4, HSR>(p, i, j, o, dg[4], rot_word(r, 13));
   }
 }
 
@@ -411,20 +433,22 @@ __device__ __forceinline__ void node_macros(const KParams<T, S>& p, int k, const
 // after step, and the slowly decaying modes of the cavity accumulate that
 // fixed rounding pattern into a bias far above one rounding.  The update is
 // therefore written as f* = a + b (a the stored population, b its change from
-// the moment changes) and added as a + (b + xi), xi uniform on
-// (-ulp(a), ulp(a)) with ulp the spacing of the storage type S at a, then
-// rounded to nearest in S (FP32: by the FP32 add; _Float16: by the store,
-// the FP32 sum being far finer than the half spacing).  A uniform dither whose
-// width is a whole number of grid spacings leaves rounding to nearest
-// unbiased, and 2 ulp(a) is one, two or four spacings at a + b (a + b one
-// binade above a, in a's binade, or one below; below the smallest normal half
-// the spacing is constant and the dither two spacings wide).  One uniform per
-// node update serves all 14
-// populations (each is still rounded without bias); it has 24 bits and comes
-// from one round of the "lowbias32" integer hash (Chris Wellons, hash
-// prospector, public domain) of the node index and three of the node's
-// incoming populations, so it is deterministic, changes from step to step as
-// the state does, and is the same in every kernel that updates the node.
+// the moment changes) and rounded to the storage type without bias:
+//   * FP32 storage: added as a + (b + xi), xi uniform on (-ulp(a), ulp(a)),
+//     then rounded to nearest by the FP32 add.  A uniform dither whose width
+//     is a whole number of grid spacings leaves rounding to nearest unbiased,
+//     and 2 ulp(a) is one, two or four spacings at a + b (a + b one binade
+//     above a, in a's binade, or one below).
+//   * half storage: a + b in FP32, then the hardware's stochastically
+//     rounding FP32 -> FP16 conversion at the store (it rounds up with the
+//     probability of the fraction of a half spacing cut off, subnormal halves
+//     included).
+// One random word per node update serves all 14 populations (each is still
+// rounded without bias); it comes from one round of the "lowbias32" integer
+// hash (Chris Wellons, hash prospector, public domain) of the node index and
+// three of the node's incoming populations, so it is deterministic, changes
+// from step to step as the state does, and is the same in every kernel that
+// updates the node.
 __device__ __forceinline__ unsigned mix32(unsigned x) {
   x ^= x >> 16;
   x *= 0x7feb352du;
@@ -434,34 +458,40 @@ __device__ __forceinline__ unsigned mix32(unsigned x) {
   return x;
 }
 
-// Storage precision: mantissa bits of S (FP32 23, _Float16 10).
-template <typename S>
-constexpr int mant_bits() { return std::is_same<S, _Float16>::value ? 10 : 23; }
+// The node's random word.
+__device__ __forceinline__ unsigned node_word(int k, float a0, float a1, float a2) {
+  return mix32((unsigned)k * 0x9e3779b1u ^ __float_as_uint(a0) ^
+               __builtin_amdgcn_alignbit(__float_as_uint(a1), __float_as_uint(a1), 11) ^
+               __builtin_amdgcn_alignbit(__float_as_uint(a2), __float_as_uint(a2), 22));
+}
 
-// The node's dither scale: u 2^-(m-1) with u uniform on (-1/2, 1/2) and m the
-// mantissa bits of S, so that us * 2^e(a) = u * 2 ulp_S(a).
-template <typename S>
-__device__ __forceinline__ float dither_scale(int k, float a0, float a1, float a2) {
-  const unsigned h = mix32((unsigned)k * 0x9e3779b1u ^ __float_as_uint(a0) ^
-                           __builtin_amdgcn_alignbit(__float_as_uint(a1), __float_as_uint(a1), 11) ^
-                           __builtin_amdgcn_alignbit(__float_as_uint(a2), __float_as_uint(a2), 22));
-  constexpr float sc = 1.0f / (float)(1u << (mant_bits<S>() - 1));
+// The FP32 dither scale: u 2^-22 with u uniform on (-1/2, 1/2) (24 bits of
+// the word), so that us * 2^e(a) = u * 2 ulp(a).
+__device__ __forceinline__ float dither_scale(unsigned h) {
+  constexpr float sc = 0x1p-22f;
   return __builtin_fmaf((float)(h >> 8), 0x1p-24f * sc, (0x1p-25f - 0.5f) * sc);
 }
 
-// a + b with the node's dither, before the rounding to S.  FP32: 2^e(a) is 0
-// for a zero or subnormal a (no dither there).  _Float16: 2^e(a) is floored
-// at the smallest normal half, 2^-14, whose ulp is the subnormal spacing.
-template <typename S>
+// a + b with the node's FP32 dither (2^e(a) is 0 for a zero or subnormal a:
+// no dither there).
 __device__ __forceinline__ float dither_add(float a, float b, float us) {
-  unsigned e = __float_as_uint(a) & 0x7f800000u;
-  if constexpr (std::is_same<S, _Float16>::value) e = max(e, 0x38800000u);  // the bits of 2^-14
+  const unsigned e = __float_as_uint(a) & 0x7f800000u;
   return a + __builtin_fmaf(us, __uint_as_float(e), b);
 }
 
+// f* = a + b ahead of its rounding to the storage type S (see above).
+template <typename S>
+__device__ __forceinline__ float sr_add(float a, float b, float us) {
+  if constexpr (std::is_same<S, _Float16>::value) return a + b;
+  else return dither_add(a, b, us);
+}
+
 // The full local update: Steps 2-9 on shifted populations, in place.
+// With SR and half storage, *rw receives the node's random word for the
+// stores' stochastic conversion (the caller passes rw then).
 template <typename T, bool POW, bool LOGDA, bool SR = false, typename S>
-__device__ __forceinline__ void collide(const KParams<T, S>& p, int k, T df[9], T dg[5]) {
+__device__ __forceinline__ void collide(const KParams<T, S>& p, int k, T df[9], T dg[5],
+                                        unsigned* rw = nullptr) {
   T drho, rho, jx, jy, dT, Gx, Gy, nu, ux, uy, invK, invsK, m1, m7, m8;
   node_macros<T, POW, LOGDA>(p, k, df, dg, drho, rho, jx, jy, dT, Gx, Gy, nu, ux, uy, invK,
                              invsK, m1, m7, m8);
@@ -505,7 +535,9 @@ __device__ __forceinline__ void collide(const KParams<T, S>& p, int k, T df[9], 
   float us = 0.0f;  // the node's dither scale (SR)
   if constexpr (SR) {
     static_assert(sizeof(T) == 4, "stochastic rounding is for FP32 compute (FP32 or FP16 storage)");
-    us = dither_scale<S>(k, df[0], dg[0], df[5]);
+    const unsigned h = node_word(k, df[0], dg[0], df[5]);
+    if constexpr (std::is_same<S, _Float16>::value) *rw = h;
+    else us = dither_scale(h);
     // the same back-transform applied to the moment changes ms - m (the
     // density is conserved), added to the incoming populations
     const T d1 = (ms1 - m1) * T(1.0 / 36.0), d2 = (ms2 - m2) * T(1.0 / 36.0);
@@ -515,15 +547,15 @@ __device__ __forceinline__ void collide(const KParams<T, S>& p, int k, T df[9], 
     const T e14 = -d1 - T(2) * d2, e58 = T(2) * d1 + d2;
     const T u1 = d3 - T(2) * d4, v1 = d5 - T(2) * d6;
     const T u5 = d3 + d4, v5 = d5 + d6;
-    df[0] = dither_add<S>(df[0], T(4) * (d2 - d1), us);
-    df[1] = dither_add<S>(df[1], (e14 + u1) + d7, us);
-    df[2] = dither_add<S>(df[2], (e14 + v1) - d7, us);
-    df[3] = dither_add<S>(df[3], (e14 - u1) + d7, us);
-    df[4] = dither_add<S>(df[4], (e14 - v1) - d7, us);
-    df[5] = dither_add<S>(df[5], (e58 + u5) + (v5 + d8), us);
-    df[6] = dither_add<S>(df[6], (e58 - u5) + (v5 - d8), us);
-    df[7] = dither_add<S>(df[7], (e58 - u5) - (v5 - d8), us);
-    df[8] = dither_add<S>(df[8], (e58 + u5) - (v5 + d8), us);
+    df[0] = sr_add<S>(df[0], T(4) * (d2 - d1), us);
+    df[1] = sr_add<S>(df[1], (e14 + u1) + d7, us);
+    df[2] = sr_add<S>(df[2], (e14 + v1) - d7, us);
+    df[3] = sr_add<S>(df[3], (e14 - u1) + d7, us);
+    df[4] = sr_add<S>(df[4], (e14 - v1) - d7, us);
+    df[5] = sr_add<S>(df[5], (e58 + u5) + (v5 + d8), us);
+    df[6] = sr_add<S>(df[6], (e58 - u5) + (v5 - d8), us);
+    df[7] = sr_add<S>(df[7], (e58 - u5) - (v5 - d8), us);
+    df[8] = sr_add<S>(df[8], (e58 + u5) - (v5 + d8), us);
   } else {
     df[0] = (a0 - T(4) * a1) + T(4) * a2;
     df[1] = (b14 + x1) + a7;
@@ -547,11 +579,11 @@ __device__ __forceinline__ void collide(const KParams<T, S>& p, int k, T df[9], 
   if constexpr (SR) {
     const T e1 = (ns1 - n1) * T(0.5), e2 = (ns2 - n2) * T(0.5);
     const T e3 = (ns3 - n3) * T(0.05), e4 = (ns4 - n4) * T(0.25);  // T is conserved
-    dg[0] = dither_add<S>(dg[0], T(-4) * e3, us);
-    dg[1] = dither_add<S>(dg[1], (e3 + e1) + e4, us);
-    dg[2] = dither_add<S>(dg[2], (e3 + e2) - e4, us);
-    dg[3] = dither_add<S>(dg[3], (e3 - e1) + e4, us);
-    dg[4] = dither_add<S>(dg[4], (e3 - e2) - e4, us);
+    dg[0] = sr_add<S>(dg[0], T(-4) * e3, us);
+    dg[1] = sr_add<S>(dg[1], (e3 + e1) + e4, us);
+    dg[2] = sr_add<S>(dg[2], (e3 + e2) - e4, us);
+    dg[3] = sr_add<S>(dg[3], (e3 - e1) + e4, us);
+    dg[4] = sr_add<S>(dg[4], (e3 - e2) - e4, us);
   } else {
     const T c0 = dT * T(0.2), c1 = ns1 * T(0.5), c2 = ns2 * T(0.5);
     const T c3 = ns3 * T(0.05), c4 = ns4 * T(0.25);
@@ -572,6 +604,8 @@ template <typename T, bool ODD, bool POW, bool LOGDA, bool SR = false, typename 
 __device__ __forceinline__ void step_tile(const KParams<T, S>& p, const KParams<T, S>& d, int i0, int j, int lx) {
   const int i = i0 + lx;
   T df[9], dg[5];
+  constexpr bool HSR = SR && std::is_same<S, _Float16>::value;  // stochastic conversion at the stores
+  unsigned rw = 0;
   if (ODD) {
     // Waves whose 64 nodes all have their 8 neighbours inside the grid take
     // the branch-free interior path (wave-uniform test; a wave covers 64
@@ -580,15 +614,15 @@ __device__ __forceinline__ void step_tile(const KParams<T, S>& p, const KParams<
     const bool interior = w0 >= 1 && w0 + 63 <= p.nx - 2 && j >= 1 && j <= p.ny - 2;
     if (interior) {
       load_interior_odd<T>(p, row_base(p, j), i, df, dg);
-      collide<T, POW, LOGDA, SR>(p, j * p.nx + i, df, dg);
-      store_interior_odd<T>(d, row_base(d, j), i, df, dg);
+      collide<T, POW, LOGDA, SR>(p, j * p.nx + i, df, dg, &rw);
+      store_interior_odd<T, HSR>(d, row_base(d, j), i, df, dg, rw);
       return;
     }
   }
   if (i >= p.nx) return;
   load_node<T, ODD>(p, i, j, df, dg);
-  collide<T, POW, LOGDA, SR>(p, j * p.nx + i, df, dg);
-  store_node<T, ODD>(d, i, j, df, dg);
+  collide<T, POW, LOGDA, SR>(p, j * p.nx + i, df, dg, &rw);
+  store_node<T, ODD, HSR>(d, i, j, df, dg, rw);
 }
 
 }  // namespace dev

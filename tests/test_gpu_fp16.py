@@ -5,16 +5,21 @@ Bars, from the measured loss of half-precision storage (a half ulp is 2^-11
 relative, against 2^-24 for FP32):
   * one step from a random non-equilibrium state: every stored population
     within two half ulps (2^-9 relative) of the oracle's step from the same
-    half-rounded state -- the stochastic rounding adds at most one ulp of
-    dither and half an ulp of rounding;
-  * 64^2 cavities after 20 000 steps from rest (measured: Newtonian fields
-    1.7e-3, Nu 7.3e-3; power law at Ra = 1e5 fields 5.6e-3, Nu 3.3e-3): fields
-    within 3e-3 (Newtonian) and 1e-2 (power law), Nu within 1.5e-2 and 1e-2.
-    Nu is limited by noise: Eq. (24) weighs the two wall columns' theta by
-    N (8 - 9 theta_0 + theta_1) / 3, so the rounding noise of the stored
-    thermal populations, about 1e-4 in theta, reaches Nu amplified about
-    twenty times at Nu ~ 1.  Round-to-nearest half storage is 20 to 70 times
-    worse (it accumulates its fixed rounding pattern in the slow modes).
+    half-rounded state -- the stochastic conversion moves a value by less
+    than one half spacing;
+  * 64^2 cavities after 20 000 steps from rest: the error is rounding noise,
+    so it is measured over realizations of it -- the rest state and seven
+    rest states perturbed by 1e-6 relative (far below the error; every
+    random word of the rounding changes).  Over 24 realizations the fields
+    were within 9.5e-4 (median) / 1.3e-3 (max) for the Newtonian cavity and
+    8.2e-3 / 9.9e-3 for the power law at Ra = 1e5, Nu within 1.5e-3 / 3.4e-3
+    and 2.1e-3 / 4.0e-3; the bars are 1.5 times those, on the median and on
+    the largest of the eight.  Nu is limited by noise: Eq. (24) weighs the
+    two wall columns' theta by N (8 - 9 theta_0 + theta_1) / 3, so the
+    rounding noise of the stored thermal populations reaches Nu amplified
+    about twenty times at Nu ~ 1.  Round-to-nearest half storage is 40 to
+    100 times worse (it accumulates its fixed rounding pattern in the slow
+    modes).
 """
 import numpy as np
 import pytest
@@ -65,19 +70,33 @@ CFG0 = dict(n=1.0, Da=0.1, Ra=1e3, Pr=10.0, eps=0.6)
 PLAW = dict(n=0.8, Da=1e-2, Ra=1e5, Pr=10.0, eps=0.6)
 
 
-@pytest.mark.parametrize("kw,bar,bar_nu", [(CFG0, 3e-3, 1.5e-2), (PLAW, 1e-2, 1e-2)],
-                         ids=["newtonian", "power-law"])
-def test_fp16_cavity_64_20000_steps(kw, bar, bar_nu):
+# (median, max) bars for the fields and for Nu, per cavity
+BARS = {"newtonian": ((1.5e-3, 2.0e-3), (2.3e-3, 5.0e-3)),
+        "power-law": ((1.25e-2, 1.5e-2), (3.2e-3, 6.0e-3))}
+
+
+@pytest.mark.parametrize("name,kw", [("newtonian", CFG0), ("power-law", PLAW)], ids=["newtonian", "power-law"])
+def test_fp16_cavity_64_20000_steps(name, kw):
     orc = oracle_for(64, **kw).step(20000)
-    out = {}
-    for rounding in ("auto", "nearest"):
-        cav = gpu_for(64, dtype="fp16", rounding=rounding, **kw)
+    fields, nus = [], []
+    for s in range(8):
+        cav = gpu_for(64, dtype="fp16", **kw)
+        if s:
+            f0, g0 = inputs.random_state(64, 64, seed=1000 + s, amp=1e-6, T0=0.5, amp_T=1e-6)
+            cav.set_populations(torch.from_numpy(f0), torch.from_numpy(g0))
         cav.step(20000)
-        errs = compare_fields(cav, orc)
-        out[rounding] = (max(errs.values()), compare_nu(cav, orc))
-        log(f"fp16 ({rounding}) 64^2 {kw}: {errs}, |dNu|/Nu {out[rounding][1]:.3e}")
-    assert out["auto"][0] <= bar and out["auto"][1] <= bar_nu
-    assert out["nearest"][0] > 3 * out["auto"][0]
+        fields.append(max(compare_fields(cav, orc).values()))
+        nus.append(compare_nu(cav, orc))
+    near = gpu_for(64, dtype="fp16", rounding="nearest", **kw)
+    near.step(20000)
+    fn = max(compare_fields(near, orc).values())
+    (fmed, fmax), (nmed, nmax) = BARS[name]
+    log(f"fp16 64^2 {name}: fields median {np.median(fields):.2e} max {max(fields):.2e}, Nu median "
+        f"{np.median(nus):.2e} max {max(nus):.2e} over 8 realizations; round-to-nearest fields {fn:.2e}, "
+        f"Nu {compare_nu(near, orc):.2e}")
+    assert np.median(fields) <= fmed and max(fields) <= fmax
+    assert np.median(nus) <= nmed and max(nus) <= nmax
+    assert fn > 3 * np.median(fields)
 
 
 def test_fp16_state_round_trip_and_checkpoint():
