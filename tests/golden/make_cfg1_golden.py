@@ -10,7 +10,7 @@ U, V, theta on every 4th node in each direction and on the two hot-wall
 columns.
 
 Run from the repository root:  python tests/golden/make_cfg1_golden.py [out.npz]
-(one to two hours on 8 cores; the default output is the path above).
+(about 85 minutes on 8 threads; the default output is the path above).
 """
 import os
 import sys

@@ -27,25 +27,18 @@ def gold():
 
 
 def errors(cav, g):
-    """Max error over every node (or, for a golden file that stores only
-    every 4th node and the two hot-wall columns, over those) relative to the
-    oracle's full-field maxima, per field; Nu."""
+    """Max error over every node relative to the oracle's full-field
+    maxima, per field; Nu."""
     U, V, T = (t.cpu().numpy() for t in cav.fields(torch.float64))
     out = {}
-    for name, a, full, sub, wall, scale in (("U", U, "U", "U4", "Uw", "maxU"), ("V", V, "V", "V4", "Vw", "maxV"),
-                                            ("theta", T, "T", "T4", "Tw", "maxT")):
-        if full in g:
-            d = np.abs(a - g[full]).max()
-        else:
-            d = max(np.abs(a[::4, ::4] - g[sub]).max(), np.abs(a[:, :2] - g[wall]).max())
-        out[name] = float(d / g[scale])
+    for name, a, ref, scale in (("U", U, "U", "maxU"), ("V", V, "V", "maxV"), ("theta", T, "T", "maxT")):
+        out[name] = float(np.abs(a - g[ref]).max() / g[scale])
     out["Nu"] = abs(cav.nu() - float(g["nu_bar"])) / float(g["nu_bar"])
     return out
 
 
-def sampled(cav):
-    U, V, T = (t.cpu().numpy() for t in cav.fields(torch.float64))
-    return [np.concatenate([a[::4, ::4].ravel(), a[:, :2].ravel()]) for a in (U, V, T)], cav.nu()
+def all_nodes(cav):
+    return [t.cpu().numpy() for t in cav.fields(torch.float64)], cav.nu()
 
 
 @pytest.fixture(scope="module")
@@ -60,7 +53,7 @@ def fp64_runs(gold):
     f0, g0 = inputs.random_state(N, N, seed=5, amp=6e-8, T0=0.5, amp_T=3e-8)
     pert.set_populations(torch.from_numpy(f0), torch.from_numpy(g0))
     pert.step(steps)
-    (a, nu_a), (b, nu_b) = sampled(cav), sampled(pert)
+    (a, nu_a), (b, nu_b) = all_nodes(cav), all_nodes(pert)
     scales = (float(gold["maxU"]), float(gold["maxV"]), float(gold["maxT"]))
     spread = max([float(np.abs(x - y).max()) / sc for x, y, sc in zip(a, b, scales)] + [abs(nu_a - nu_b) / nu_a])
     return cav, r, steps, spread
@@ -83,7 +76,7 @@ def test_fp64_stops_at_the_oracle_step_with_the_oracle_state(gold, fp64_runs):
 def test_fp32_at_the_oracle_step(gold):
     """FP32 storage and arithmetic with round-to-nearest updates
     (PM_ROUND_NEAREST), run for exactly S* steps (the FP64 stopping step).
-    Measured: U 4.8e-4, V 1.9e-4, theta 2.4e-4, Nu 2.4e-4 -- above the 1e-4
+    Measured: U 4.8e-4, V 2.0e-4, theta 2.4e-4, Nu 2.4e-4 -- above the 1e-4
     FP32 bar: near the steady flow the same state rounds the same way every
     step and the slowly decaying low-shear power-law mode sums that fixed
     pattern into a bias (FP64 arithmetic on FP32-rounded populations gives
