@@ -22,6 +22,10 @@ node by two steps per launch, at 4096^2 FP32):
     really moves per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, committed
     with a hash of the kernel code) over the launch time, against the peak
     and against the measured streaming-copy ceiling;
+  * counters: VALU instructions per node update, the share of the CU's
+    VALU issue rate they take and the share of wave time spent waiting
+    (rocprofv3 SQ counters, committed with the same hash) -- what the kernel
+    is bound by besides HBM;
 and the other FP32 rounding mode, the adjoint/forward cost of the gradient
 workload, a capped comparison of the 27-case sweep with sequential runs, and
 the FP64 CPU oracle timed on a bounded sample of the same workload on this
@@ -143,6 +147,33 @@ def read_traffic(kind="pair"):
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+SQ_COUNTERS = os.path.join(ROOT, "profiles", "step_kernels_4096_sq_counters.txt")
+
+
+def read_counters(kind="pair"):
+    """VALU instructions per node update, VALU issue share and wait share of
+    a step kernel from the committed SQ counter summary, or None when absent
+    or taken on different kernel code (the summary records the code hash of
+    each kernel family)."""
+    if not os.path.exists(SQ_COUNTERS):
+        return None
+    family = "pair" if kind.startswith("pair") else "single"
+    text = open(SQ_COUNTERS).read()
+    m = re.search(r"bench\.kernel_hash\('%s'\) = ([0-9a-f]+)" % family, text)
+    if m is None or m.group(1) != kernel_hash(kind):
+        return None
+    m = re.search(r"^%s: (.*)$" % re.escape(kind), text, flags=re.M)
+    if m is None:
+        return None
+    vals = dict(kv.split(" = ") for kv in m.group(1).split(", "))
+    try:
+        return {"valu_per_node_update": float(vals["valu_per_node_update"]),
+                "valu_issue_share": float(vals["valu_issue_share"]),
+                "wait_share": float(vals["wait_share"])}
     except (KeyError, ValueError):
         return None
 
@@ -586,6 +617,7 @@ def main():
                      "hbm_GBps": round(hbm, 1) if hbm else None,
                      "hbm_frac": round(hbm / HBM_PEAK_GBS, 4) if hbm else None,
                      "copy_frac": round(hbm / copy_gbs, 4) if hbm else None,
+                     "counters": read_counters(kind),
                      "alg_equiv_GBps": round(alg_equiv, 1),
                      "alg_equiv_frac": round(alg_equiv / HBM_PEAK_GBS, 4),
                      "kernel": K["name"],

@@ -44,6 +44,19 @@ def test_traffic_only_for_the_measured_kernel_code(kind, monkeypatch):
     assert bench.read_traffic(kind) is None
 
 
+@pytest.mark.parametrize("kind", ["pair", "pair_sr", "single_sr", "single_fp16"])
+def test_counters_only_for_the_measured_kernel_code(kind, monkeypatch):
+    text = open(bench.SQ_COUNTERS).read()
+    fam = "pair" if kind.startswith("pair") else "single"
+    recorded = text.split(f"bench.kernel_hash('{fam}') = ")[1][:16]
+    monkeypatch.setattr(bench, "kernel_hash", lambda k="pair": recorded)
+    c = bench.read_counters(kind)
+    assert c is not None and 0 < c["valu_issue_share"] <= 1 and 0 <= c["wait_share"] <= 1
+    assert c["valu_per_node_update"] > 100
+    monkeypatch.setattr(bench, "kernel_hash", lambda k="pair": "0" * 16)
+    assert bench.read_counters(kind) is None
+
+
 @pytest.mark.parametrize("kind", sorted(bench.KERNELS))
 def test_kernel_hash_follows_code_not_comments(kind, tmp_path, monkeypatch):
     srcs = []
