@@ -9,7 +9,9 @@ Recipes (numpy.random.default_rng):
   * smooth perturbation direction of the log10(Da) field: rng(seed) normal
     coefficients of cos(pi a x) cos(pi b y), a, b in 0..2;
   * random population states (parity tests): rest weights times
-    (1 + amp * standard normal), thermal weights times (T0 + amp_T * normal).
+    (1 + amp * standard normal), thermal weights times (T0 + amp_T * normal);
+  * uniform population states: one such draw of the 9 + 5 populations,
+    repeated at every node.
 """
 import itertools
 
@@ -60,3 +62,13 @@ def smooth_direction(N, seed=5):
         for b in range(3):
             w = w + rng.standard_normal() * np.cos(np.pi * a * x) * np.cos(np.pi * b * y)
     return w
+
+
+def uniform_state(nx, ny, seed, amp=0.03, T0=0.5, amp_T=0.2):
+    """One random node state (as random_state draws it) repeated at every
+    node: f [9, ny, nx], g [5, ny, nx]."""
+    rng = np.random.default_rng(seed)
+    f = W9 * (1 + amp * rng.standard_normal(9))
+    g = W5 * (T0 + amp_T * rng.standard_normal(5))
+    return (np.repeat(np.repeat(f[:, None, None], ny, 1), nx, 2),
+            np.repeat(np.repeat(g[:, None, None], ny, 1), nx, 2))

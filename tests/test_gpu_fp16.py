@@ -66,6 +66,67 @@ def test_fp16_step_within_two_half_ulps(kw, pre):
     log(f"fp16 one step {kw} pre={pre}: worst error {worst:.3f} of the two-half-ulp bound")
 
 
+def _bracket(exact):
+    """The two halves (as float64 arrays) that bracket each value of exact."""
+    h = exact.astype(np.float16)
+    above = h.astype(np.float64) > exact
+    down = np.nextafter(h, np.float16(-np.inf)).astype(np.float64)
+    up = np.nextafter(h, np.float16(np.inf)).astype(np.float64)
+    hv = h.astype(np.float64)
+    return np.where(above, down, hv), np.where(above, hv, up)
+
+
+@pytest.mark.parametrize("pre", [0, 1])
+def test_fp16_stochastic_rounding_is_unbiased(pre):
+    """A uniform state on a doubly periodic 64 x 64 grid (after one more step
+    for the odd parity): every node computes its update in FP32 and stores,
+    chosen by its own random word, one of the two halves that bracket it.
+    Over the 4096 nodes the mean rounding error of every population is
+    within 0.05 of a half spacing (its standard deviation is at most 0.008
+    spacing).  Checked for the populations whose shifted value is at least
+    a tenth of the largest one's: there the FP32 arithmetic before the
+    rounding is within a few thousandths of a half spacing of the oracle's
+    FP64 value (smaller ones, down to subnormal halves, are only reported).
+    Round-to-nearest storage is off by its fixed rounding error instead."""
+    N = 64
+    kw = dict(n=0.7, Da=1e-2, Ra=1e4, Pr=10.0, eps=0.6, periodic_x=1, periodic_y=1)
+    f0, g0 = inputs.uniform_state(N, N, seed=21)
+    worst, checked = {}, []
+    for rounding in ("auto", "nearest"):
+        cav = gpu_for(N, N, dtype="fp16", rounding=rounding, **kw)
+        cav.set_populations(torch.from_numpy(f0), torch.from_numpy(g0))
+        cav.step(pre)
+        fh, gh = (t.cpu().numpy() for t in cav.populations(torch.float64))
+        orc = oracle_for(N, N, **kw)
+        orc.set_state(fh, gh)
+        orc.step(1)
+        fr, gr = orc.state()
+        cav.step(1)
+        fg, gg = (t.cpu().numpy() for t in cav.populations(torch.float64))
+        biases, checked = [], []
+        # the library shifts by the FP32 weights; with them, got - w is the
+        # stored half exactly and ref - w the update it was rounded from
+        for got, ref, w in ((fg, fr, W9.astype(np.float32).astype(np.float64)),
+                            (gg, gr, W5.astype(np.float32).astype(np.float64) * 0.5)):
+            big = max(abs(ref[q].mean() - w[q]) for q in range(got.shape[0]))
+            for q in range(got.shape[0]):
+                exact = ref[q] - w[q]                 # the shifted values the kernels store
+                lo, hi = _bracket(exact)
+                sp = hi - lo
+                stored = got[q] - w[q]
+                biases.append(float(((stored - exact) / sp).mean()))
+                if abs(exact.mean()) >= 0.1 * big:
+                    near = np.minimum(np.abs(stored - lo), np.abs(stored - hi)) / sp
+                    assert near.max() <= 0.02, (rounding, q, near.max())   # one of the two bracketing halves
+                    checked.append(abs(biases[-1]))
+        worst[rounding] = max(checked)
+        log(f"fp16 uniform state, {rounding}, pre={pre}: mean rounding error in half spacings "
+            f"{np.round(biases, 3).tolist()}")
+    assert len(checked) >= 10
+    assert worst["auto"] <= 0.05
+    assert worst["nearest"] > 0.1
+
+
 CFG0 = dict(n=1.0, Da=0.1, Ra=1e3, Pr=10.0, eps=0.6)
 PLAW = dict(n=0.8, Da=1e-2, Ra=1e5, Pr=10.0, eps=0.6)
 
