@@ -29,7 +29,7 @@ node by two steps per launch, at 4096^2 FP32):
 and the other FP32 rounding mode, the adjoint/forward cost of the gradient
 workload, a capped comparison of the 27-case sweep with sequential runs, and
 the FP64 CPU oracle timed on a bounded sample of the same workload on this
-host (all cores and one core).
+host (all cores and one core), with its rates on the other parity workloads.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-extras]
        python bench.py --sweep | --adjoint | --paper-tables | --stream-function | --oracle-table
@@ -273,10 +273,10 @@ def _oracle_rates(one_core):
     return out
 
 
-def oracle_table_main(args):
+def oracle_table():
     """The FP64 oracle's throughput on the parity workloads, on all the
     host's cores and on one core (a child process), with the wall time a
-    whole run would take at that rate."""
+    whole run would take at that rate (about 25 s of CPU time in all)."""
     import subprocess
     threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
     log(f"oracle table: {threads} threads")
@@ -292,6 +292,11 @@ def oracle_table_main(args):
         a.update({k + "_1core": b[k] for k in ("steps_sampled", "seconds", "mlups", "est_full_run_s")})
         log(f"oracle table: {a['workload']}: {a['mlups']} MLUPS on {threads} threads, "
             f"{a['mlups_1core']} on one core")
+    return rows, threads
+
+
+def oracle_table_main(args):
+    rows, threads = oracle_table()
     print(json.dumps({"metric": "oracle MLUPS", "unit": "MLUPS", "kind": "oracle", "dtype": "f64",
                       "cpu_model": cpu_model(), "cores": threads, "workloads": rows}), flush=True)
 
@@ -510,7 +515,8 @@ def main():
     ap.add_argument("--rounding", default=None, choices=["nearest", "stochastic"],
                     help="rounding of the FP32 population updates (PM_ROUND_*; default: the library's)")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the other rounding mode, the adjoint cost and the capped sweep")
+                    help="skip the other rounding mode, the adjoint cost, the capped sweep and the oracle's "
+                         "rates on the other parity workloads")
     ap.add_argument("--sweep-extra-cap", type=int, default=10000,
                     help="step cap of the capped 27-case sweep comparison in the default run")
     ap.add_argument("--roofline-steps", type=int, default=400)
@@ -647,6 +653,11 @@ def main():
         torch.cuda.empty_cache()
         log("bench: timing the CPU oracle on a bounded sample ...")
         result["cpu_baseline"] = cpu_baseline()
+        if not args.no_extras:
+            try:
+                result["cpu_baseline"]["workloads"] = oracle_table()[0]
+            except Exception as e:  # a failed CPU sample must not cost the GPU line
+                log(f"bench: oracle table not measured: {type(e).__name__}: {e}")
     print(json.dumps(result), flush=True)
 
 
