@@ -119,7 +119,24 @@ __global__ __launch_bounds__(TILE) void k_step2(KParams<float> src, KParams<floa
   __shared__ float ring1[3][NXS][TILE];  // f* of rows a - 2 .. a
   __shared__ float ring2[3][NXS][TILE];  // f** of rows a - 3 .. a - 1
   const int t = threadIdx.x;
-  const int x0 = blockIdx.x * PAIR_W, y0 = blockIdx.y * rows;
+  // Tile of this workgroup.  The dispatcher deals consecutive workgroups to
+  // the 8 XCDs in turn; tiles (row group major, strip minor) are dealt to
+  // them in blocks of XCD_BLOCK adjacent strips instead, so that a strip's
+  // halo columns, which its neighbours also read, are mostly fetched into
+  // the same XCD's L2, while all XCDs still advance through the same rows.
+  // The last G mod (8 XCD_BLOCK) workgroups keep their own tile (the map is
+  // a bijection on the tiles).
+  constexpr int XCD_BLOCK = 8;
+  const int G = gridDim.x * gridDim.y;
+  const int L = blockIdx.y * gridDim.x + blockIdx.x;
+  const int Gf = G / (8 * XCD_BLOCK) * (8 * XCD_BLOCK);
+  int tl = L;
+  if (L < Gf) {
+    const int xcd = L & 7, q = L >> 3;
+    tl = ((q / XCD_BLOCK) * 8 + xcd) * XCD_BLOCK + q % XCD_BLOCK;
+  }
+  const int sy = tl / (int)gridDim.x, sx = tl - sy * (int)gridDim.x;
+  const int x0 = sx * PAIR_W, y0 = sy * rows;
   const int c = x0 - 2 + t;
   const bool col = c >= 0 && c < src.nx;
   const int y_end = min(y0 + rows, src.ny);  // output rows [y0, y_end)
