@@ -547,7 +547,7 @@ def test_stream_function_tall_grid(dtype):
         assert err <= 1e-12
 
 
-PAIR_SIZES = [(8, 8), (33, 21), (252, 70), (300, 130), (520, 67)]
+PAIR_SIZES = [(8, 8), (33, 21), (252, 70), (300, 130), (520, 67), (1100, 400)]
 
 
 @pytest.mark.parametrize("size", PAIR_SIZES)
@@ -557,9 +557,11 @@ def test_two_step_kernel_equals_single_steps(size, n, logda, rounding):
     """The two-step kernel (forced with PM_STEP_PAIR: by default it runs only
     on grids large enough to fill the GPU) against the single-step kernel:
     both must give the same populations bit for bit -- on grids narrower and
-    wider than one 252-column strip, with partial 24-row chunks -- from a
-    random state, and across a graph-replayed run (k >= 128, starting at an
-    odd step count)."""
+    wider than one 252-column strip, with partial 24-row chunks, and on
+    1100 x 400 (5 strips x 25 row groups), whose first 64 tiles are dealt to
+    the XCDs in blocks and the rest in launch order -- from a random state,
+    and across a graph-replayed run (k >= 128, starting at an odd step
+    count)."""
     nx, ny = size
     kw = dict(n=n, Da=1e-2, Ra=1e5, Pr=10.0, eps=0.6, rounding=rounding)
     ld = inputs.logda_field(max(nx, ny), seed=2)[:ny, :nx].copy() if logda else None
