@@ -409,3 +409,22 @@ def test_per_cell_permeability_two_layers():
                 assert np.abs(uu - ua).max() / ua.max() > 0.1
         errs.append(np.abs(o.macros()["ux"][:, 0] - ua).max() / ua.max())
     assert errs[2] < 3e-3 and errs[0] / errs[1] > 3 and errs[1] / errs[2] > 3, errs
+
+
+def test_hot_and_cold_wall_nusselt_balance_at_steady_state():
+    """At steady state the heat entering through the hot wall leaves through
+    the cold wall, so Eq. (24) evaluated at either wall (the one-sided
+    quadratic gradient through the wall value and the first two nodes) gives
+    the same Nusselt number up to discretisation error, which shrinks with
+    the grid.  Also: the oracle's Nu is Eq. (24) applied to its own fields."""
+    out = []
+    for N in (24, 32):
+        o = O.Oracle.from_physics(O.physics(N, n=1.0, Da=1e-2, Ra=1e4, Pr=5.0, eps=0.6))
+        r, _ = o.run_to_steady(tol=1e-12, check_every=1000, max_steps=200_000)
+        assert r < 1e-12
+        _, _, th = o.fields()
+        hot = np.mean(N * (8.0 - 9.0 * th[:, 0] + th[:, 1]) / 3.0)
+        cold = np.mean(N * (9.0 * th[:, -1] - th[:, -2]) / 3.0)
+        assert o.nu_bar() == pytest.approx(hot, rel=1e-14)
+        out.append(abs(hot - cold) / hot)
+    assert out[0] < 1e-4 and out[1] < out[0] / 2, out
