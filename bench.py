@@ -423,7 +423,7 @@ def paper_main(args):
 
 
 def adjoint_main(args):
-    """Cost of the gradient of Nu_bar on the 256 x 256 cavity (FP32 forward
+    """Cost of the gradient of Nu_bar on the 256 x 256 cavity (or --adjoint-side; FP32 forward
     state, FP64 adjoint, n = 0.7, Ra = 1e4, per-cell log10 Da ~ U[-3, -1]
     seed 0, T = 5000 steps, checkpoints every ceil(sqrt(T)) steps): forward
     with checkpoints vs backward (segment replay + adjoint steps).  With the
@@ -435,7 +435,7 @@ def adjoint_main(args):
     import paper_2011_15073_amd as P
     from paper_2011_15073_amd import inputs
 
-    N, T = 256, args.adjoint_steps
+    N, T = args.adjoint_side, args.adjoint_steps
     ld = torch.from_numpy(inputs.logda_field(N, seed=0))
     times = []
     for rep in range(2):
@@ -457,7 +457,7 @@ def adjoint_main(args):
         "metric": "adjoint/forward cost", "value": round(bwd / fwd, 3), "unit": "x",
         "n_gpus": 1, "higher_is_better": False, "dtype": "f32 forward / f64 adjoint",
         "data": "synthetic",
-        "config": {"workload": "256x256 porous cavity, n=0.7, Ra=1e4, Pr=10, eps=0.6, per-cell "
+        "config": {"workload": f"{N}x{N} porous cavity, n=0.7, Ra=1e4, Pr=10, eps=0.6, per-cell "
                                "log10 Da ~ U[-3,-1] (seed 0), J = Nu_bar after T steps",
                    "T": T, "checkpoint_every": math.ceil(math.sqrt(T)),
                    "shear_floor": args.adjoint_shear_floor},
@@ -544,6 +544,8 @@ def main():
     ap.add_argument("--oracle-table", action="store_true",
                     help="time the FP64 CPU oracle on the parity workloads (all cores and one core); no GPU")
     ap.add_argument("--adjoint-steps", type=int, default=5000)
+    ap.add_argument("--adjoint-side", type=int, default=256,
+                    help="grid side of the adjoint benchmark (default 256, the gradient workload)")
     ap.add_argument("--adjoint-shear-floor", type=float, default=0.1,
                     help="nondimensional shear floor of the regularised adjoint (0: exact)")
     args = ap.parse_args()
