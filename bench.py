@@ -430,7 +430,8 @@ def adjoint_main(args):
     [0.1, 10] viscosity clamp the exact adjoint of this workload grows without
     bound (low-shear regions amplify perturbations), so the gradient is taken
     with the shear floor gamma* = --adjoint-shear-floor; the work per step is
-    the same either way."""
+    the same either way.  --adjoint-lambda fp32 stores the adjoint state in
+    FP32 between steps (FP64 arithmetic)."""
     import torch
     import paper_2011_15073_amd as P
     from paper_2011_15073_amd import inputs
@@ -440,7 +441,7 @@ def adjoint_main(args):
     times = []
     for rep in range(2):
         cav = P.Cavity(N, dtype="fp32", logda=ld, n=0.7, Ra=1e4, Pr=10.0, eps=0.6)
-        adj = P.Adjoint(cav, T, shear_floor=args.adjoint_shear_floor)
+        adj = P.Adjoint(cav, T, shear_floor=args.adjoint_shear_floor, lambda_dtype=args.adjoint_lambda)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         J = adj.forward()
@@ -455,7 +456,8 @@ def adjoint_main(args):
     fwd, bwd = times[-1]
     print(json.dumps({
         "metric": "adjoint/forward cost", "value": round(bwd / fwd, 3), "unit": "x",
-        "n_gpus": 1, "higher_is_better": False, "dtype": "f32 forward / f64 adjoint",
+        "n_gpus": 1, "higher_is_better": False,
+        "dtype": "f32 forward / f64 adjoint" + (", f32 adjoint state" if args.adjoint_lambda == "fp32" else ""),
         "data": "synthetic",
         "config": {"workload": f"{N}x{N} porous cavity, n=0.7, Ra=1e4, Pr=10, eps=0.6, per-cell "
                                "log10 Da ~ U[-3,-1] (seed 0), J = Nu_bar after T steps",
@@ -548,6 +550,8 @@ def main():
                     help="grid side of the adjoint benchmark (default 256, the gradient workload)")
     ap.add_argument("--adjoint-shear-floor", type=float, default=0.1,
                     help="nondimensional shear floor of the regularised adjoint (0: exact)")
+    ap.add_argument("--adjoint-lambda", choices=("fp64", "fp32"), default="fp64",
+                    help="storage of the adjoint state between steps (FP64 arithmetic either way)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "

@@ -346,6 +346,15 @@ int pm_adjoint_backward(pm_adjoint* a, double seed, void* grad_logda, double* gr
  * amplify perturbations from step to step; the floor removes that channel.
  * PM_EINVAL for a negative or non-finite value. */
 int pm_adjoint_set_shear_floor(pm_adjoint* a, double gamma_floor);
+/* Storage of the adjoint state between steps: PM_FP64 (default) or PM_FP32,
+ * for FP32 forward states only (else PM_EINVAL).  The adjoint arithmetic
+ * stays FP64; with PM_FP32 each step's result is rounded to nearest FP32
+ * before it is stored, which halves the adjoint state's memory traffic (the
+ * adjoint step then moves 188 B per node instead of 300) at a relative cost
+ * in the gradients of the order of the FP32 forward's own rounding.  The
+ * workspace size does not depend on it.  Takes effect at the next
+ * pm_adjoint_backward. */
+int pm_adjoint_set_lambda_dtype(pm_adjoint* a, int dtype);
 void pm_adjoint_destroy(pm_adjoint* a);
 const char* pm_adjoint_last_error(const pm_adjoint* a);
 

@@ -31,7 +31,8 @@ EXPORTS = [
     "pm_sweep_advance", "pm_sweep_status",
     "pm_sweep_step", "pm_sweep_case", "pm_sweep_destroy", "pm_sweep_last_error",
     "pm_adjoint_workspace_bytes", "pm_adjoint_create", "pm_adjoint_forward",
-    "pm_adjoint_backward", "pm_adjoint_set_shear_floor", "pm_adjoint_destroy", "pm_adjoint_last_error",
+    "pm_adjoint_backward", "pm_adjoint_set_shear_floor", "pm_adjoint_set_lambda_dtype", "pm_adjoint_destroy",
+    "pm_adjoint_last_error",
     "pm_adjoint_vjp_scratch_bytes", "pm_adjoint_vjp", "pm_adjoint_vjp_noalloc",
     "pm_strerror", "pm_last_error",
 ]
@@ -112,6 +113,7 @@ def _load():
         "pm_adjoint_forward": ([vp, P(dbl)], i32),
         "pm_adjoint_backward": ([vp, dbl, vp, P(dbl), P(dbl)], i32),
         "pm_adjoint_set_shear_floor": ([vp, dbl], i32),
+        "pm_adjoint_set_lambda_dtype": ([vp, i32], i32),
         "pm_adjoint_destroy": ([vp], None),
         "pm_adjoint_last_error": ([vp], C.c_char_p),
         "pm_adjoint_vjp_scratch_bytes": ([vp], sz),

@@ -12,14 +12,19 @@ import math
 
 import torch
 
-from ._lib import check, lib
+from ._lib import PM_FP32, check, lib
 from .cavity import Cavity
 
 
 class Adjoint:
-    """Forward run with checkpoints + backward sweep for one cavity."""
+    """Forward run with checkpoints + backward sweep for one cavity.
 
-    def __init__(self, cavity: Cavity, T: int, C_every: int = None, shear_floor: float = 0.0):
+    ``lambda_dtype="fp32"`` (FP32 cavities only) stores the adjoint state in
+    FP32 between steps, halving its memory traffic; the arithmetic stays FP64.
+    """
+
+    def __init__(self, cavity: Cavity, T: int, C_every: int = None, shear_floor: float = 0.0,
+                 lambda_dtype: str = "fp64"):
         self.cav = cavity
         self.T = int(T)
         self.C = int(C_every or math.ceil(math.sqrt(T)))
@@ -33,6 +38,10 @@ class Adjoint:
         self._h = h
         if shear_floor:
             self._check(lib.pm_adjoint_set_shear_floor(self._h, float(shear_floor)))
+        if lambda_dtype not in ("fp64", "fp32"):
+            raise ValueError(f"lambda_dtype must be 'fp64' or 'fp32', not {lambda_dtype!r}")
+        if lambda_dtype == "fp32":
+            self._check(lib.pm_adjoint_set_lambda_dtype(self._h, PM_FP32))
 
     def _check(self, rc):
         return check(rc, self._h, lib.pm_adjoint_last_error)

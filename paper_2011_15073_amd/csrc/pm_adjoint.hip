@@ -49,10 +49,12 @@ __device__ __forceinline__ NuSol nu_fp64(const AdjParams& a, double A, double B)
   // Start: the closed-form root for A << B s^2, 3 nu >> 1/2, refined by a few
   // FP32 Newton steps on the hardware exp2 / log2 / reciprocal (about 1e-6 in
   // y), so that the FP64 Newton steps below converge in two or three.
-  float yf = (float)((a.lc0 + a.nm1 * (0.5 * log2(B) - 1.584962500721156181453738943947816508)) * a.inv_n);
+  float yf;
   {
     const float lo = (float)a.y_lo, hi = (float)a.y_hi, lc0 = (float)a.lc0, nm1 = (float)a.nm1;
     const float Af = (float)A, Bf = (float)B;
+    // log2(0) = -inf (no shear, or B below the FP32 range) lands on a bound
+    yf = (lc0 + nm1 * (0.5f * __builtin_amdgcn_logf(Bf) - 1.5849625007f)) * (float)a.inv_n;
     yf = fminf(fmaxf(yf, lo), hi);
     for (int it = 0; it < 6; ++it) {
       const float nu = __builtin_amdgcn_exp2f(yf);
@@ -383,65 +385,97 @@ __device__ __forceinline__ void vjp_node(const AdjParams& a, const double df[9],
 // neighbour, and the node itself at a wall) and written once, so the loads
 // here and the stores in k_adjoint are non-temporal; measured 2-8% faster per
 // launch from 256^2 to 4096^2 than cached accesses.
-__device__ __forceinline__ void gather_mu(const AdjParams& a, const double* __restrict__ lam, int i, int j,
-                                          double mf[9], double mg[5]) {
+// The adjoint state is stored as L: double, or float for FP32 forward states
+// (the arithmetic stays FP64; only the values kept between steps are
+// rounded, to nearest).  gather_mu only loads; mu_signs then applies the
+// anti-bounce-back sign of the Dirichlet walls, so that no arithmetic on a
+// loaded value (and no wait for it) sits between the node's loads.
+// Every address below is a select between two indices whose row parts are
+// wave-uniform (j is the workgroup's row) and whose column part is the lane's,
+// with the inside test as a bitwise and: no branches between the loads.
+template <typename L>
+__device__ __forceinline__ void gather_mu(const AdjParams& a, const L* __restrict__ lam, int i, int j,
+                                          L rf[9], L rg[5]) {
   const int nx = a.nx, ny = a.ny;
   const int64_t nn = (int64_t)nx * ny, k = (int64_t)j * nx + i;
+  const bool in_ip = i + 1 < nx, in_im = i >= 1, in_jp = j + 1 < ny, in_jm = j >= 1;
+  const int64_t r0 = (int64_t)j * nx;
 #pragma unroll
-  for (int q = 0; q < 9; ++q) {
-    const int di = i + EXv[q], dj = j + EYv[q];
-    const bool in = di >= 0 && di < nx && dj >= 0 && dj < ny;
-    const double* src = in ? &lam[q * nn + (int64_t)dj * nx + di] : &lam[OPP[q] * nn + k];
-    mf[q] = __builtin_nontemporal_load(src);
-  }
-#pragma unroll
-  for (int q = 0; q < 5; ++q) {
-    const int di = i + EXv[q], dj = j + EYv[q];
-    const bool in = di >= 0 && di < nx && dj >= 0 && dj < ny;
-    const double* src = in ? &lam[(9 + q) * nn + (int64_t)dj * nx + di] : &lam[(9 + OPP[q]) * nn + k];
-    double v = __builtin_nontemporal_load(src);
-    if (!in && EXv[q] != 0) v = -v;  // anti-bounce-back at the Dirichlet walls
-    mg[q] = v;
+  for (int q = 0; q < 14; ++q) {
+    const int d = q < 9 ? q : q - 9;  // direction within D2Q9 / D2Q5
+    const int od = OPP[d] + (q < 9 ? 0 : 9);
+    const bool in = (EXv[d] > 0 ? in_ip : (EXv[d] < 0 ? in_im : true)) &
+                    (EYv[d] > 0 ? in_jp : (EYv[d] < 0 ? in_jm : true));
+    const int64_t idx = in ? q * nn + r0 + EYv[d] * (int64_t)nx + (i + EXv[d]) : od * nn + k;
+    const L v = __builtin_nontemporal_load(&lam[idx]);
+    if (q < 9) rf[q] = v;
+    else rg[q - 9] = v;
   }
 }
 
-template <typename S>
-__global__ __launch_bounds__(TILE) void k_adjoint(KParams<S> st, AdjParams a, int parity,
-                                                  const double* __restrict__ lam_next,
-                                                  double* __restrict__ lam, double* __restrict__ g_logda,
+template <typename L>
+__device__ __forceinline__ void mu_signs(const AdjParams& a, int i, const L rf[9], const L rg[5], double mf[9],
+                                         double mg[5]) {
+#pragma unroll
+  for (int q = 0; q < 9; ++q) mf[q] = (double)rf[q];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    const double v = (double)rg[q];
+    const bool wall = (EXv[q] == 1 && i + 1 >= a.nx) || (EXv[q] == -1 && i == 0);
+    mg[q] = wall ? -v : v;  // anti-bounce-back at the hot and cold walls
+  }
+}
+
+// ODD: the parity of the step whose state is read (a template parameter, so
+// that each variant's loads are one straight-line sequence).
+template <typename S, typename L, bool ODD>
+__global__ __launch_bounds__(TILE) void k_adjoint(KParams<S> st, AdjParams a,
+                                                  const L* __restrict__ lam_next,
+                                                  L* __restrict__ lam, double* __restrict__ g_logda,
                                                   double* __restrict__ partial) {
   __shared__ double red[ADJ_PART][TILE];
   const int tiles_x = (a.nx + TILE - 1) / TILE;
   const int j = blockIdx.x / tiles_x;
   const int i = (blockIdx.x - j * tiles_x) * TILE + threadIdx.x;
   double c_lnnu0 = 0.0, c_n = 0.0, c_sg = 0.0, lmax = 0.0;
+  // The workgroup's partials and the node's gradient are read, updated and
+  // written back; their reads are issued with the node's loads, so that the
+  // end of the wave does not wait on a load.
+  double p_old = 0.0;
+  if (threadIdx.x < ADJ_PART) p_old = partial[ADJ_PART * blockIdx.x + threadIdx.x];
   if (i < a.nx) {
+    // Loads in this order: lambda_{k+1}, the old gradient, the state (whose
+    // wall conditions need their values), log10 Da.  Each wait then covers
+    // loads that are all in flight already: one memory round trip.
+    const int64_t k = (int64_t)j * a.nx + i, nn = (int64_t)a.nx * a.ny;
+    L rf[9], rg[5];
+    gather_mu(a, lam_next, i, j, rf, rg);
+    const double gl_old = a.has_logda ? g_logda[k] : 0.0;
     S sf[9], sg[5];
-    if (parity) load_node<S, true>(st, i, j, sf, sg);
-    else load_node<S, false>(st, i, j, sf, sg);
+    load_node_raw<S, ODD>(st, i, j, sf, sg);
+    const double ld = a.has_logda ? (double)st.logda[k] : 0.0;
+    if (ODD) pull_walls(st, i, sg);
     double df[9], dg[5], mf[9], mg[5], lf[9], lg[5];
 #pragma unroll
     for (int q = 0; q < 9; ++q) df[q] = (double)sf[q];
 #pragma unroll
     for (int q = 0; q < 5; ++q) dg[q] = (double)sg[q];
-    const int64_t k = (int64_t)j * a.nx + i, nn = (int64_t)a.nx * a.ny;
-    const double ld = a.has_logda ? (double)st.logda[k] : 0.0;
-    gather_mu(a, lam_next, i, j, mf, mg);
+    mu_signs(a, i, rf, rg, mf, mg);
     double g_ld;
     vjp_node(a, df, dg, ld, mf, mg, lf, lg, g_ld, c_lnnu0, c_n, c_sg);
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
-      __builtin_nontemporal_store(lf[q], &lam[q * nn + k]);
+      __builtin_nontemporal_store((L)lf[q], &lam[q * nn + k]);
       lmax = fmax(lmax, fabs(lf[q]));
       if (lf[q] != lf[q]) lmax = INFINITY;  // NaN counts as unbounded
     }
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
-      __builtin_nontemporal_store(lg[q], &lam[(9 + q) * nn + k]);
+      __builtin_nontemporal_store((L)lg[q], &lam[(9 + q) * nn + k]);
       lmax = fmax(lmax, fabs(lg[q]));
       if (lg[q] != lg[q]) lmax = INFINITY;
     }
-    if (a.has_logda) g_logda[k] += g_ld;
+    if (a.has_logda) g_logda[k] = gl_old + g_ld;
   }
   red[0][threadIdx.x] = c_lnnu0;
   red[1][threadIdx.x] = c_n;
@@ -457,14 +491,14 @@ __global__ __launch_bounds__(TILE) void k_adjoint(KParams<S> st, AdjParams a, in
     }
     __syncthreads();
   }
-  if (threadIdx.x < 3) partial[ADJ_PART * blockIdx.x + threadIdx.x] += red[threadIdx.x][0];
-  if (threadIdx.x == 3)
-    partial[ADJ_PART * blockIdx.x + 3] = fmax(partial[ADJ_PART * blockIdx.x + 3], red[3][0]);
+  if (threadIdx.x < 3) partial[ADJ_PART * blockIdx.x + threadIdx.x] = p_old + red[threadIdx.x][0];
+  if (threadIdx.x == 3) partial[ADJ_PART * blockIdx.x + 3] = fmax(p_old, red[3][0]);
 }
 
 // lambda_T = dJ/dS_T for J = Nu_bar (Eq. 24): only the thermal populations of
 // the two hot-wall columns contribute.
-__global__ void k_adjoint_seed(int nx, int ny, double seed, double* __restrict__ lam) {
+template <typename L>
+__global__ void k_adjoint_seed(int nx, int ny, double seed, L* __restrict__ lam) {
   const int64_t nn = (int64_t)nx * ny;
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < 14 * nn;
        t += (int64_t)gridDim.x * blockDim.x) {
@@ -476,7 +510,7 @@ __global__ void k_adjoint_seed(int nx, int ny, double seed, double* __restrict__
       if (i == 0) v = -3.0 * nx / (double)ny;
       else if (i == 1) v = nx / (3.0 * ny);
     }
-    lam[t] = seed * v;
+    lam[t] = (L)(seed * v);
   }
 }
 
@@ -516,26 +550,35 @@ hipError_t launch_adj_reduce(const double* partial, int nblocks, double* out, hi
   return hipGetLastError();
 }
 
-template <typename S>
-hipError_t launch_adjoint(const KParams<S>& st, const AdjParams& a, int parity, const double* lam_next,
-                          double* lam, double* g_logda, double* partial, hipStream_t s) {
+template <typename S, typename L>
+hipError_t launch_adjoint(const KParams<S>& st, const AdjParams& a, int parity, const L* lam_next, L* lam,
+                          double* g_logda, double* partial, hipStream_t s) {
   const int tiles_x = (a.nx + TILE - 1) / TILE;
-  hipLaunchKernelGGL((k_adjoint<S>), dim3(tiles_x * a.ny), dim3(TILE), 0, s, st, a, parity, lam_next, lam,
-                     g_logda, partial);
+  if (parity)
+    hipLaunchKernelGGL((k_adjoint<S, L, true>), dim3(tiles_x * a.ny), dim3(TILE), 0, s, st, a, lam_next, lam,
+                       g_logda, partial);
+  else
+    hipLaunchKernelGGL((k_adjoint<S, L, false>), dim3(tiles_x * a.ny), dim3(TILE), 0, s, st, a, lam_next, lam,
+                       g_logda, partial);
   return hipGetLastError();
 }
 
-hipError_t launch_adjoint_seed(int nx, int ny, double seed, double* lam, hipStream_t s) {
+template <typename L>
+hipError_t launch_adjoint_seed(int nx, int ny, double seed, L* lam, hipStream_t s) {
   const int64_t n = 14 * (int64_t)nx * ny;
   int64_t b = (n + 255) / 256;
   if (b > 65536) b = 65536;
-  hipLaunchKernelGGL(k_adjoint_seed, dim3((unsigned)b), dim3(256), 0, s, nx, ny, seed, lam);
+  hipLaunchKernelGGL((k_adjoint_seed<L>), dim3((unsigned)b), dim3(256), 0, s, nx, ny, seed, lam);
   return hipGetLastError();
 }
 
-template hipError_t launch_adjoint<float>(const KParams<float>&, const AdjParams&, int, const double*, double*,
-                                          double*, double*, hipStream_t);
-template hipError_t launch_adjoint<double>(const KParams<double>&, const AdjParams&, int, const double*,
-                                           double*, double*, double*, hipStream_t);
+template hipError_t launch_adjoint<float, double>(const KParams<float>&, const AdjParams&, int, const double*,
+                                                  double*, double*, double*, hipStream_t);
+template hipError_t launch_adjoint<float, float>(const KParams<float>&, const AdjParams&, int, const float*,
+                                                 float*, double*, double*, hipStream_t);
+template hipError_t launch_adjoint<double, double>(const KParams<double>&, const AdjParams&, int, const double*,
+                                                   double*, double*, double*, hipStream_t);
+template hipError_t launch_adjoint_seed<double>(int, int, double, double*, hipStream_t);
+template hipError_t launch_adjoint_seed<float>(int, int, double, float*, hipStream_t);
 
 }  // namespace pm

@@ -1236,7 +1236,8 @@ struct pm_adjoint {
   char* seg[2];         // C + 1 states of a replayed segment, double-buffered
   hipStream_t replay;   // segment replays run here, one segment ahead of the adjoint
   hipEvent_t ev_start, ev_rep[2], ev_used[2];
-  double* lam[2];       // adjoint state, natural layout [14][ny][nx]
+  void* lam[2];         // adjoint state, natural layout [14][ny][nx], FP64 or FP32 (lam_dtype)
+  int lam_dtype;        // PM_FP64 (default) or PM_FP32
   double* partial;      // pm::ADJ_PART doubles per workgroup
   int nblocks;
   double J;
@@ -1354,10 +1355,17 @@ int adj_fail(pm_adjoint* a, int code, const char* fmt, ...) {
 hipError_t adj_step(const pm_ctx* c, const pm::AdjParams& ap, char* state, int parity, const double* lam_next,
                     double* lam, double* g_logda, double* partial) {
   if (c->p.dtype == PM_FP64)
-    return pm::launch_adjoint<double>(slot_params<double>(c, c->k64, state), ap, parity, lam_next, lam, g_logda,
-                                      partial, c->stream);
-  return pm::launch_adjoint<float>(slot_params<float>(c, c->k32, state), ap, parity, lam_next, lam, g_logda,
-                                   partial, c->stream);
+    return pm::launch_adjoint<double, double>(slot_params<double>(c, c->k64, state), ap, parity, lam_next, lam,
+                                              g_logda, partial, c->stream);
+  return pm::launch_adjoint<float, double>(slot_params<float>(c, c->k32, state), ap, parity, lam_next, lam,
+                                           g_logda, partial, c->stream);
+}
+
+// The same with an FP32-stored adjoint state (FP32 forward states only).
+hipError_t adj_step(const pm_ctx* c, const pm::AdjParams& ap, char* state, int parity, const float* lam_next,
+                    float* lam, double* g_logda, double* partial) {
+  return pm::launch_adjoint<float, float>(slot_params<float>(c, c->k32, state), ap, parity, lam_next, lam,
+                                          g_logda, partial, c->stream);
 }
 
 // Chain rule from the per-node parameters (ln nu0, n at fixed nu0, s_g) to
@@ -1439,8 +1447,9 @@ int pm_adjoint_create(pm_ctx* c, int64_t T, int64_t C, void* dev_ws, size_t ws_b
   a->cp = b + A.off_cp;
   a->seg[0] = b + A.off_seg;
   a->seg[1] = a->seg[0] + (C + 1) * align_up(A.span);
-  a->lam[0] = (double*)(b + A.off_lam0);
-  a->lam[1] = (double*)(b + A.off_lam1);
+  a->lam[0] = b + A.off_lam0;
+  a->lam[1] = b + A.off_lam1;
+  a->lam_dtype = PM_FP64;
   a->partial = (double*)(b + A.off_partial);
   a->nblocks = A.nblocks;
   a->ap = adj_params(c);
@@ -1476,7 +1485,10 @@ int pm_adjoint_backward(pm_adjoint* a, double seed, void* grad_logda, double* gr
   const int64_t nn = (int64_t)c->p.nx * c->p.ny;
   hipError_t e = hipMemsetAsync(a->partial, 0, pm::ADJ_PART * (size_t)a->nblocks * sizeof(double), c->stream);
   if (e == hipSuccess && grad_logda) e = hipMemsetAsync(grad_logda, 0, nn * sizeof(double), c->stream);
-  if (e == hipSuccess) e = pm::launch_adjoint_seed(c->p.nx, c->p.ny, seed, a->lam[0], c->stream);
+  const bool lam32 = a->lam_dtype == PM_FP32;
+  if (e == hipSuccess)
+    e = lam32 ? pm::launch_adjoint_seed(c->p.nx, c->p.ny, seed, (float*)a->lam[0], c->stream)
+              : pm::launch_adjoint_seed(c->p.nx, c->p.ny, seed, (double*)a->lam[0], c->stream);
   if (e != hipSuccess) return adj_fail(a, PM_EDEVICE, "backward setup: %s", hipGetErrorString(e));
   const size_t stride = align_up(a->span);
   const bool logda = c->p.has_logda != 0;
@@ -1522,8 +1534,11 @@ int pm_adjoint_backward(pm_adjoint* a, double seed, void* grad_logda, double* gr
     const int64_t n = std::min(a->C, a->T - start);
     for (int64_t t = n - 1; t >= 0 && e == hipSuccess; --t) {
       const int parity = (int)((a->s0 + start + t) & 1);
-      e = adj_step(c, a->ap, a->seg[b] + t * stride, parity, a->lam[cur], a->lam[cur ^ 1], (double*)grad_logda,
-                   a->partial);
+      char* st = a->seg[b] + t * stride;
+      e = lam32 ? adj_step(c, a->ap, st, parity, (const float*)a->lam[cur], (float*)a->lam[cur ^ 1],
+                           (double*)grad_logda, a->partial)
+                : adj_step(c, a->ap, st, parity, (const double*)a->lam[cur], (double*)a->lam[cur ^ 1],
+                           (double*)grad_logda, a->partial);
       cur ^= 1;
     }
     if (e == hipSuccess) e = hipEventRecord(a->ev_used[b], c->stream);
@@ -1555,6 +1570,16 @@ int pm_adjoint_set_shear_floor(pm_adjoint* a, double gamma_floor) {
     return adj_fail(a, PM_EINVAL, "pm_adjoint_set_shear_floor: need a finite gamma_floor >= 0");
   const double g = gamma_floor / a->ctx->L.gamma_scale;  // nondimensional -> lattice
   a->ap.g2_floor = g * g;
+  return PM_OK;
+}
+
+int pm_adjoint_set_lambda_dtype(pm_adjoint* a, int dtype) {
+  if (!a) return PM_EINVAL;
+  if (dtype != PM_FP64 && dtype != PM_FP32)
+    return adj_fail(a, PM_EINVAL, "pm_adjoint_set_lambda_dtype: PM_FP64 or PM_FP32");
+  if (dtype == PM_FP32 && a->ctx->p.dtype != PM_FP32)
+    return adj_fail(a, PM_EINVAL, "pm_adjoint_set_lambda_dtype: an FP32 adjoint state needs FP32 forward states");
+  a->lam_dtype = dtype;
   return PM_OK;
 }
 

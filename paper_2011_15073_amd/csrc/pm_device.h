@@ -232,29 +232,58 @@ __device__ __forceinline__ void store_interior_odd(const KParams<T, S>& p, const
 
 // Pre-collision populations of node (i, j) for a state of the given parity.
 template <typename T, bool ODD, typename S>
-__device__ __forceinline__ void load_node(const KParams<T, S>& p, int i, int j, T df[9], T dg[5]) {
+__device__ __forceinline__ void load_node_raw(const KParams<T, S>& p, int i, int j, T df[9], T dg[5]) {
   const int64_t o = pop_off(p, i, j);
   if (!ODD) {
 #pragma unroll
     for (int q = 0; q < 9; ++q) df[q] = ldg<T, true>(p.f + q * p.qs + o);
 #pragma unroll
     for (int q = 0; q < 5; ++q) dg[q] = ldg<T, true>(p.g + q * p.qs + o);
-  } else {
-    df[0] = ldg<T, true>(p.f + o);
-    df[1] = pull_f<T, 1>(p, i, j, o);
-    df[2] = pull_f<T, 2>(p, i, j, o);
-    df[3] = pull_f<T, 3>(p, i, j, o);
-    df[4] = pull_f<T, 4>(p, i, j, o);
-    df[5] = pull_f<T, 5>(p, i, j, o);
-    df[6] = pull_f<T, 6>(p, i, j, o);
-    df[7] = pull_f<T, 7>(p, i, j, o);
-    df[8] = pull_f<T, 8>(p, i, j, o);
-    dg[0] = ldg<T, true>(p.g + o);
-    dg[1] = pull_g<T, 1>(p, i, j, o);
-    dg[2] = pull_g<T, 2>(p, i, j, o);
-    dg[3] = pull_g<T, 3>(p, i, j, o);
-    dg[4] = pull_g<T, 4>(p, i, j, o);
+    return;
   }
+  // The pulls of pull_f / pull_g without the thermal wall conditions (see
+  // pull_walls).  The source column (i - 1, i or i + 1, wrapped on a
+  // periodic axis) and row (j - 1, j or j + 1: wave-uniform) and whether
+  // each is inside are worked out once; each address is then a select
+  // between two indices, so no branch separates the 14 loads and all of
+  // them are in flight before any value is used.
+  const int nx = p.nx, ny = p.ny;
+  const int im = p.px && i == 0 ? nx - 1 : i - 1;       // source column of e_x = +1
+  const int ip = p.px && i == nx - 1 ? 0 : i + 1;       // of e_x = -1
+  const bool in_im = p.px || i >= 1, in_ip = p.px || i + 1 < nx;
+  const int jm = p.py && j == 0 ? ny - 1 : j - 1;       // source row of e_y = +1
+  const int jp = p.py && j == ny - 1 ? 0 : j + 1;       // of e_y = -1
+  const bool in_jm = p.py || j >= 1, in_jp = p.py || j + 1 < ny;
+  const int64_t rm = (int64_t)jm * p.rs, r0 = (int64_t)j * p.rs, rp = (int64_t)jp * p.rs;
+#pragma unroll
+  for (int q = 0; q < 14; ++q) {
+    const int d = q < 9 ? q : q - 9;  // direction within D2Q9 / D2Q5
+    const S* base = q < 9 ? p.f : p.g;
+    const int si = EXv[d] > 0 ? im : (EXv[d] < 0 ? ip : i);
+    const int64_t rs = EYv[d] > 0 ? rm : (EYv[d] < 0 ? rp : r0);
+    const bool in = (EXv[d] > 0 ? in_im : (EXv[d] < 0 ? in_ip : true)) &
+                    (EYv[d] > 0 ? in_jm : (EYv[d] < 0 ? in_jp : true));
+    const int64_t idx = in ? OPP[d] * p.qs + rs + si : d * p.qs + o;
+    const T v = EXv[d] == 0 ? ldg<T, true>(base + idx) : ldg<T, false>(base + idx);
+    if (q < 9) df[q] = v;
+    else dg[q - 9] = v;
+  }
+}
+
+// The thermal conditions of the odd step's pull, as in pull_g: at the hot
+// wall (x = 0) the pulled dg_1 is hotc - dg_1 as loaded, at the cold wall
+// (x = nx - 1) the pulled dg_3 is coldc - dg_3 (anti-bounce-back).
+template <typename T, typename S>
+__device__ __forceinline__ void pull_walls(const KParams<T, S>& p, int i, T dg[5]) {
+  const bool hot = !p.px & (i == 0), cold = !p.px & (i == p.nx - 1);  // selects, no branch
+  dg[1] = hot ? p.hotc - dg[1] : dg[1];
+  dg[3] = cold ? p.coldc - dg[3] : dg[3];
+}
+
+template <typename T, bool ODD, typename S>
+__device__ __forceinline__ void load_node(const KParams<T, S>& p, int i, int j, T df[9], T dg[5]) {
+  load_node_raw<T, ODD>(p, i, j, df, dg);
+  if (ODD) pull_walls(p, i, dg);
 }
 
 template <typename T, bool ODD, typename S>
@@ -282,20 +311,34 @@ __device__ __forceinline__ void store_node(const KParams<T, S>& p, int i, int j,
 #pragma unroll
     for (int q = 0; q < 5; ++q) stg<T, true, HSR>(p.g + OPP[q] * p.qs + o, dg[q], rot_word(r, 9 + q));
   } else {
-    stg<T, true, HSR>(p.f + o, df[0], r);
-    push_f<T, 1, HSR>(p, i, j, o, df[1], rot_word(r, 1));
-    push_f<T, 2, HSR>(p, i, j, o, df[2], rot_word(r, 2));
-    push_f<T, 3, HSR>(p, i, j, o, df[3], rot_word(r, 3));
-    push_f<T, 4, HSR>(p, i, j, o, df[4], rot_word(r, 4));
-    push_f<T, 5, HSR>(p, i, j, o, df[5], rot_word(r, 5));
-    push_f<T, 6, HSR>(p, i, j, o, df[6], rot_word(r, 6));
-    push_f<T, 7, HSR>(p, i, j, o, df[7], rot_word(r, 7));
-    push_f<T, 8, HSR>(p, i, j, o, df[8], rot_word(r, 8));
-    stg<T, true, HSR>(p.g + o, dg[0], rot_word(r, 9));
-    push_g<T, 1, HSR>(p, i, j, o, dg[1], rot_word(r, 10));
-    push_g<T, 2, HSR>(p, i, j, o, dg[2], rot_word(r, 11));
-    push_g<T, 3, HSR>(p, i, j, o, dg[3], rot_word(r, 12));
-    push_g<T, 4, HSR>(p, i, j, o, dg[4], rot_word(r, 13));
+    // The pushes of push_f / push_g, with the destination column (i + 1,
+    // i or i - 1, wrapped on a periodic axis), row (wave-uniform) and inside
+    // tests worked out once and each address a select between two indices.
+    const int nx = p.nx, ny = p.ny;
+    const int ip = p.px && i == nx - 1 ? 0 : i + 1;  // destination column of e_x = +1
+    const int im = p.px && i == 0 ? nx - 1 : i - 1;  // of e_x = -1
+    const bool in_ip = p.px || i + 1 < nx, in_im = p.px || i >= 1;
+    const int jp = p.py && j == ny - 1 ? 0 : j + 1;  // destination row of e_y = +1
+    const int jm = p.py && j == 0 ? ny - 1 : j - 1;  // of e_y = -1
+    const bool in_jp = p.py || j + 1 < ny, in_jm = p.py || j >= 1;
+    const int64_t rp = (int64_t)jp * p.rs, r0 = (int64_t)j * p.rs, rm = (int64_t)jm * p.rs;
+#pragma unroll
+    for (int q = 0; q < 14; ++q) {
+      const int d = q < 9 ? q : q - 9;  // direction within D2Q9 / D2Q5
+      S* base = q < 9 ? p.f : p.g;
+      const int di = EXv[d] > 0 ? ip : (EXv[d] < 0 ? im : i);
+      const int64_t rs = EYv[d] > 0 ? rp : (EYv[d] < 0 ? rm : r0);
+      const bool in = (EXv[d] > 0 ? in_ip : (EXv[d] < 0 ? in_im : true)) &
+                      (EYv[d] > 0 ? in_jp : (EYv[d] < 0 ? in_jm : true));
+      const int64_t idx = in ? d * p.qs + rs + di : OPP[d] * p.qs + o;
+      T w = q < 9 ? df[d] : dg[d];
+      // thermal populations leaving through the hot (x = 0) or cold (x = nx)
+      // wall come back anti-bounced, as in push_g
+      if (q >= 9 && EXv[d] == -1) w = in ? w : p.hotc - w;
+      if (q >= 9 && EXv[d] == 1) w = in ? w : p.coldc - w;
+      if (EXv[d] == 0) stg<T, true, HSR>(base + idx, w, rot_word(r, q));
+      else stg<T, false, HSR>(base + idx, w, rot_word(r, q));
+    }
   }
 }
 
@@ -380,6 +423,8 @@ __device__ __forceinline__ void node_macros(const KParams<T, S>& p, int k, const
                                             const T dg[5], T& drho, T& rho, T& jx, T& jy,
                                             T& dT, T& Gx, T& Gy, T& nu, T& ux, T& uy, T& invK,
                                             T& invsK, T& m1, T& m7, T& m8) {
+  // read first, so that the load is in flight with the node's populations
+  const T ldk = LOGDA ? (T)p.logda[k] : T(0);
   drho = (df[0] + ((df[1] + df[2]) + (df[3] + df[4]))) + ((df[5] + df[6]) + (df[7] + df[8]));
   rho = T(1) + drho;
   jx = ((df[1] - df[3]) + (df[5] - df[6])) - (df[7] - df[8]);
@@ -414,7 +459,7 @@ __device__ __forceinline__ void node_macros(const KParams<T, S>& p, int k, const
   // Step 6: porous velocity u = v / (c0 + sqrt(c0^2 + c1 |v|))
   if (LOGDA) {
     // K = 10^logDa N^2
-    invK = fexp2<T>(T(-3.321928094887362347870319) * p.logda[k]) * p.inv_Kscale;
+    invK = fexp2<T>(T(-3.321928094887362347870319) * ldk) * p.inv_Kscale;
     invsK = fsqrt<T>(invK);
   } else {
     invK = p.invK;

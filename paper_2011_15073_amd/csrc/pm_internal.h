@@ -154,10 +154,12 @@ template <typename T>
 hipError_t launch_resid_multi(const SweepCase<T>* cases, int ncases, const int2* sched, int* live,
                               int nsched, int parity, int tw, int th, double* partial, SweepStatus* st,
                               int64_t chunk, double tol, int64_t max_steps, hipStream_t s);
-template <typename S>
-hipError_t launch_adjoint(const KParams<S>& st, const AdjParams& a, int parity, const double* lam_next,
-                          double* lam, double* g_logda, double* partial, hipStream_t s);
-hipError_t launch_adjoint_seed(int nx, int ny, double seed, double* lam, hipStream_t s);
+// L: storage type of the adjoint state (double; float for FP32 states)
+template <typename S, typename L>
+hipError_t launch_adjoint(const KParams<S>& st, const AdjParams& a, int parity, const L* lam_next, L* lam,
+                          double* g_logda, double* partial, hipStream_t s);
+template <typename L>
+hipError_t launch_adjoint_seed(int nx, int ny, double seed, L* lam, hipStream_t s);
 // a[0, n) := 0 (a fill kernel, so that callers may capture it in a graph)
 hipError_t launch_fill_zero(double* a, int64_t n, hipStream_t s);
 // the adjoint partials of nblocks workgroups reduced in workgroup order into out[ADJ_PART]

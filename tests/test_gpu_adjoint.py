@@ -176,7 +176,7 @@ def fd_at(entries, h):
     return next(e["fd"] for e in entries if e["h"] == h)
 
 
-def fd_cells_check(variant, kw, dtype, tol=1e-3):
+def fd_cells_check(variant, kw, dtype, tol=1e-3, lambda_dtype="fp64"):
     gold = oracle_fd(variant)
     ld = inputs.logda_field(N4, seed=0)
     assert gold["cells"] == [int(c) for c in inputs.fd_cells(N4, seed=1, k=16)]
@@ -184,12 +184,12 @@ def fd_cells_check(variant, kw, dtype, tol=1e-3):
     base.update(kw)
     n, Ra = base.pop("n"), base.pop("Ra")
     cav = P.Cavity(N4, dtype=dtype, logda=torch.from_numpy(ld), n=n, Ra=Ra, **base)
-    adj = P.Adjoint(cav, T4)
+    adj = P.Adjoint(cav, T4, lambda_dtype=lambda_dtype)
     J = adj.forward()
     gld, gn, gRa = adj.backward()
     g = gld.cpu().numpy()
     scale = np.abs(g).max()
-    print(f"{variant} {dtype}: J = {J:.10f} (oracle {gold['J']:.10f}), dJ/dn = {gn:.6e}, dJ/dRa = {gRa:.6e}, "
+    print(f"{variant} {dtype} (adjoint state {lambda_dtype}): J = {J:.10f} (oracle {gold['J']:.10f}), dJ/dn = {gn:.6e}, dJ/dRa = {gRa:.6e}, "
           f"max|dJ/dlogDa| = {scale:.3e}", flush=True)
     assert J == pytest.approx(gold["J"], rel=1e-4 if dtype == "fp32" else 1e-10)
     for cell, e in zip(gold["cells"], gold["cell_fd"]):
@@ -213,6 +213,46 @@ def test_256_cavity_gradients_match_oracle_finite_differences(variant, kw, dtype
     [0.1, 2] clamp the forward state is FP64: an FP32 state's own round-off
     moves the smallest cell gradients by up to 2e-3 of that floor."""
     fd_cells_check(variant, kw, dtype)
+
+
+@pytest.mark.parametrize("variant,kw", [("n1.0", dict(n=1.0)), ("n1.4", dict(n=1.4))], ids=["n1.0", "n1.4"])
+def test_256_cavity_fp32_adjoint_state_matches_oracle_finite_differences(variant, kw):
+    """The same check with the adjoint state stored in FP32 between steps
+    (FP64 arithmetic), at the same 1e-3 bar."""
+    fd_cells_check(variant, kw, "fp32", lambda_dtype="fp32")
+
+
+def test_fp32_adjoint_state_tracks_the_fp64_adjoint_state():
+    """The same FP32 forward twice, with the adjoint state stored in FP64
+    and in FP32.  Rounding the stored state to FP32 perturbs each step's
+    values by at most 2^-24 relative; over T = 5000 steps of a stable adjoint
+    recursion such perturbations add up like a random walk, ~sqrt(T) 2^-24 =
+    4e-6 relative, so the two gradients must agree to 1e-4 (of each scalar,
+    and of the largest log-Da gradient for the field)."""
+    ld = inputs.logda_field(N4, seed=0)
+    out = {}
+    for lam in ("fp64", "fp32"):
+        c = P.Cavity(N4, dtype="fp32", logda=torch.from_numpy(ld), n=1.0, Ra=1e4, **PHYS)
+        adj = P.Adjoint(c, T4, lambda_dtype=lam)
+        J = adj.forward()
+        gld, gn, gRa = adj.backward()
+        out[lam] = (J, gld.cpu().numpy(), gn, gRa)
+        adj.close()
+    (Ja, ga, na, ra), (Jb, gb, nb, rb) = out["fp64"], out["fp32"]
+    dg = np.abs(ga - gb).max() / np.abs(ga).max()
+    print(f"J {Ja:.10f} / {Jb:.10f}; dJ/dn {na:.9e} / {nb:.9e} ({abs(nb / na - 1):.2e}); "
+          f"dJ/dRa {ra:.9e} / {rb:.9e} ({abs(rb / ra - 1):.2e}); field {dg:.2e}", flush=True)
+    assert Ja == Jb
+    assert nb == pytest.approx(na, rel=1e-4) and rb == pytest.approx(ra, rel=1e-4)
+    assert dg <= 1e-4
+
+
+def test_fp32_adjoint_state_needs_an_fp32_forward():
+    cav = P.Cavity(32, dtype="fp64", n=1.0, Ra=1e4, **PHYS)
+    with pytest.raises(P.PmError, match="FP32 forward"):
+        P.Adjoint(cav, 10, lambda_dtype="fp32")
+    with pytest.raises(ValueError):
+        P.Adjoint(P.Cavity(32, dtype="fp32", n=1.0, Ra=1e4, **PHYS), 10, lambda_dtype="fp16")
 
 
 def test_256_cavity_n07_exact_adjoint_reports_amplification():
