@@ -746,13 +746,15 @@ def adjoint_cost(P, T, shear_floor):
     """The gradient workload (256^2, FP32 forward state, n = 0.7, Ra = 1e4,
     per-cell log10 Da seed 0, J = Nu_bar after T steps): backward (segment
     replays + adjoint steps) over forward (with checkpoints), wall clock,
-    second of two repetitions."""
+    second of two repetitions; then once more with the adjoint state stored
+    in FP32 between steps (pm_adjoint_set_lambda_dtype)."""
     import torch
     from paper_2011_15073_amd import inputs
     ld = torch.from_numpy(inputs.logda_field(256, seed=0))
-    for rep in range(2):
+    times = {}
+    for lam in ("fp64", "fp64", "fp32"):
         cav = P.Cavity(256, dtype="fp32", logda=ld, n=0.7, Ra=1e4, Pr=10.0, eps=0.6)
-        adj = P.Adjoint(cav, T, shear_floor=shear_floor)
+        adj = P.Adjoint(cav, T, shear_floor=shear_floor, lambda_dtype=lam)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         J = adj.forward()
@@ -760,11 +762,15 @@ def adjoint_cost(P, T, shear_floor):
         adj.backward()
         torch.cuda.synchronize()
         t2 = time.perf_counter()
+        times[lam] = (t1 - t0, t2 - t1)
         adj.close()
         del adj, cav
-    log(f"bench: adjoint {T} steps: forward {t1 - t0:.4f} s, backward {t2 - t1:.4f} s")
-    return {"adjoint_over_forward": round((t2 - t1) / (t1 - t0), 3), "forward_s": round(t1 - t0, 4),
-            "backward_s": round(t2 - t1, 4), "T": T, "J": J, "shear_floor": shear_floor,
+    (f64, b64), (f32, b32) = times["fp64"], times["fp32"]
+    log(f"bench: adjoint {T} steps: forward {f64:.4f} s, backward {b64:.4f} s (FP32 adjoint state: {b32:.4f} s)")
+    return {"adjoint_over_forward": round(b64 / f64, 3), "forward_s": round(f64, 4),
+            "backward_s": round(b64, 4),
+            "adjoint_over_forward_fp32_adjoint_state": round(b32 / f32, 3),
+            "T": T, "J": J, "shear_floor": shear_floor,
             "workload": "256x256, n=0.7, Ra=1e4, Pr=10, eps=0.6, log10 Da ~ U[-3,-1] (seed 0), FP32 forward / "
                         "FP64 adjoint, checkpoints every ceil(sqrt(T)) steps"}
 

@@ -72,7 +72,11 @@ __device__ __forceinline__ NuSol nu_fp64(const AdjParams& a, double A, double B)
   // max(n, 1) and G'' is of order |n - 1|, so a step of size d leaves an
   // error of order d^2.  A step below 1e-9 therefore ends the iteration
   // (the error left is below 1e-17) without a further step to confirm it;
-  // from the FP32 start that is two FP64 steps.
+  // from the FP32 start that is two FP64 steps.  nu at the last iterate is
+  // then 2^y of the one before times 2^d = 1 + t + t^2/2 (t = d ln 2, the
+  // next term below 1e-28): no further exp2.
+  double nu_last = 0.0, d_last = 0.0;
+  bool conv = false;
   for (int it = 0; it < 60; ++it) {
     const double nu = exp2(y);
     const double s = 1.0 / (3.0 * nu + 0.5);
@@ -82,12 +86,21 @@ __device__ __forceinline__ NuSol nu_fp64(const AdjParams& a, double A, double B)
     double yn = y - G / dG;
     if (!(g2 > 0.0)) yn = G < 0.0 ? a.y_hi : a.y_lo;
     yn = fmin(fmax(yn, a.y_lo), a.y_hi);
-    const double d = fabs(yn - y);
+    d_last = yn - y;
+    nu_last = nu;
     y = yn;
-    if (d <= 1e-9) break;
+    if (fabs(d_last) <= 1e-9) {
+      conv = true;
+      break;
+    }
   }
   r.y = y;
-  r.nu = exp2(y);
+  if (conv) {
+    const double t = d_last * LN2;
+    r.nu = nu_last * (1.0 + t * (1.0 + 0.5 * t));
+  } else {
+    r.nu = exp2(y);
+  }
   r.s = 1.0 / (3.0 * r.nu + 0.5);
   r.g2 = A + B * r.s * r.s;
   r.Gp = 1.0 + 3.0 * a.nm1 * B * r.s * r.s * r.s * r.nu / r.g2;
@@ -324,7 +337,11 @@ __device__ __forceinline__ void vjp_node(const AdjParams& a, const double df[9],
     // power law is singular in n and its one-sided limits sit on a clamp,
     // which does not depend on n at fixed nu0: no n or shear terms.
     if (ns.g2 > 0.0) {
-      g_n += w * (a.log2c + 0.5 * log2(ns.g2));  // G_n = -log2(gamma*)
+      // G_n = -log2(gamma*).  At the root G = 0 gives log2(g2) = (y - lc0) / hn
+      // (to the root's error over hn; the log is taken where hn is small).
+      const double hn = 0.5 * a.nm1;
+      const double l2g2 = fabs(hn) >= 1e-3 ? (ns.y - a.lc0) / hn : log2(ns.g2);
+      g_n += w * (a.log2c + 0.5 * l2g2);
       if (ns.g2 > a.g2_floor) {
         const double wg = w * 0.5 * a.nm1 * ILN2 / ns.g2;
         b_A += wg;
@@ -433,7 +450,9 @@ __global__ __launch_bounds__(TILE) void k_adjoint(KParams<S> st, AdjParams a,
                                                   const L* __restrict__ lam_next,
                                                   L* __restrict__ lam, double* __restrict__ g_logda,
                                                   double* __restrict__ partial) {
-  __shared__ double red[ADJ_PART][TILE];
+  static_assert(TILE % 64 == 0, "whole waves per workgroup");
+  constexpr int NW = TILE / 64;  // waves per workgroup
+  __shared__ double red[ADJ_PART][NW];
   const int tiles_x = (a.nx + TILE - 1) / TILE;
   const int j = blockIdx.x / tiles_x;
   const int i = (blockIdx.x - j * tiles_x) * TILE + threadIdx.x;
@@ -477,22 +496,30 @@ __global__ __launch_bounds__(TILE) void k_adjoint(KParams<S> st, AdjParams a,
     }
     if (a.has_logda) g_logda[k] = gl_old + g_ld;
   }
-  red[0][threadIdx.x] = c_lnnu0;
-  red[1][threadIdx.x] = c_n;
-  red[2][threadIdx.x] = c_sg;
-  red[3][threadIdx.x] = lmax;
-  __syncthreads();
-  for (int s = TILE / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) {
-      red[0][threadIdx.x] += red[0][threadIdx.x + s];
-      red[1][threadIdx.x] += red[1][threadIdx.x + s];
-      red[2][threadIdx.x] += red[2][threadIdx.x + s];
-      red[3][threadIdx.x] = fmax(red[3][threadIdx.x], red[3][threadIdx.x + s]);
-    }
-    __syncthreads();
+  // Workgroup sums (and the max): a butterfly over the 64 lanes of each
+  // wave, then the NW wave results in wave order, in one fixed order.
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    c_lnnu0 += __shfl_xor(c_lnnu0, off);
+    c_n += __shfl_xor(c_n, off);
+    c_sg += __shfl_xor(c_sg, off);
+    lmax = fmax(lmax, __shfl_xor(lmax, off));
   }
-  if (threadIdx.x < 3) partial[ADJ_PART * blockIdx.x + threadIdx.x] = p_old + red[threadIdx.x][0];
-  if (threadIdx.x == 3) partial[ADJ_PART * blockIdx.x + 3] = fmax(p_old, red[3][0]);
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red[0][wv] = c_lnnu0;
+    red[1][wv] = c_n;
+    red[2][wv] = c_sg;
+    red[3][wv] = lmax;
+  }
+  __syncthreads();
+  if (threadIdx.x < ADJ_PART) {
+    const int q = threadIdx.x;
+    double v = red[q][0];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) v = q < 3 ? v + red[q][w] : fmax(v, red[q][w]);
+    partial[ADJ_PART * blockIdx.x + q] = q < 3 ? p_old + v : fmax(p_old, v);
+  }
 }
 
 // lambda_T = dJ/dS_T for J = Nu_bar (Eq. 24): only the thermal populations of
