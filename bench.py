@@ -810,6 +810,7 @@ def sweep_capped(P, cap, dtype="fp64"):
     nupd = sum(st * c["N"] ** 2 for st, c in zip(steps, cs))
     return {"speedup_vs_sequential": round(t_s / t_b, 3), "batched_s": round(t_b, 3),
             "sequential_s": round(t_s, 3), "batched_MLUPS": round(nupd / t_b / 1e6, 1),
+            "cases_per_s": round(len(cases) / t_b, 2), "sequential_cases_per_s": round(len(cases) / t_s, 2),
             "cases_bitwise_equal": f"{same}/{len(cases)}", "cap": cap, "dtype": dtype,
             "schedule": {"order": sched["order"], "tile": list(sched["tile"])},
             "workload": "27 cases n x Da x Ra, eps=0.6, Pr=10, sides from {128,...,512} (seed 0), "
