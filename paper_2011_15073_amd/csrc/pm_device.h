@@ -133,26 +133,11 @@ __device__ __forceinline__ bool nbr(int nx, int ny, int px, int py, int i, int j
   return in;
 }
 
-// o = pop_off(p, i, j) of the node itself.
-template <typename T, int Q, typename S>
-__device__ __forceinline__ T pull_f(const KParams<T, S>& p, int i, int j, int64_t o) {
-  int si, sj;
-  const bool in = nbr<Q>(p.nx, p.ny, p.px, p.py, i, j, -1, -1, si, sj);
-  const S* a = in ? (p.f + OPP[Q] * p.qs + pop_off(p, si, sj)) : (p.f + Q * p.qs + o);
-  return ldg<T, EXv[Q] == 0>(a);
-}
-
-template <typename T, int Q, bool HSR = false, typename S>
-__device__ __forceinline__ void push_f(const KParams<T, S>& p, int i, int j, int64_t o, T v, unsigned r = 0) {
-  int di, dj;
-  const bool in = nbr<Q>(p.nx, p.ny, p.px, p.py, i, j, 1, 1, di, dj);
-  S* a = in ? (p.f + Q * p.qs + pop_off(p, di, dj)) : (p.f + OPP[Q] * p.qs + o);
-  stg<T, EXv[Q] == 0, HSR>(a, v, r);
-}
-
-// Thermal pull: across x = 0 the incoming dg_1 is -dg*_3 + hotc (anti-bounce-
-// back, hot wall), across x = nx the incoming dg_3 is -dg*_1 + coldc (cold
-// wall), across y = 0, ny plain bounce-back (adiabatic).
+// Thermal pull (o = pop_off(p, i, j) of the node itself): across x = 0 the
+// incoming dg_1 is -dg*_3 + hotc (anti-bounce-back, hot wall), across x = nx
+// the incoming dg_3 is -dg*_1 + coldc (cold wall), across y = 0, ny plain
+// bounce-back (adiabatic).  load_g uses it; the step kernels use
+// load_node_raw and pull_walls, which compute the same.
 template <typename T, int Q, typename S>
 __device__ __forceinline__ T pull_g(const KParams<T, S>& p, int i, int j, int64_t o) {
   int si, sj;
@@ -162,17 +147,6 @@ __device__ __forceinline__ T pull_g(const KParams<T, S>& p, int i, int j, int64_
   if (EXv[Q] == 1) v = in ? v : p.hotc - v;
   if (EXv[Q] == -1) v = in ? v : p.coldc - v;
   return v;
-}
-
-template <typename T, int Q, bool HSR = false, typename S>
-__device__ __forceinline__ void push_g(const KParams<T, S>& p, int i, int j, int64_t o, T v, unsigned r = 0) {
-  int di, dj;
-  const bool in = nbr<Q>(p.nx, p.ny, p.px, p.py, i, j, 1, 1, di, dj);
-  S* a = in ? (p.g + Q * p.qs + pop_off(p, di, dj)) : (p.g + OPP[Q] * p.qs + o);
-  T w = v;
-  if (EXv[Q] == -1) w = in ? v : p.hotc - v;  // leaves through x = 0
-  if (EXv[Q] == 1) w = in ? v : p.coldc - v;  // leaves through x = nx
-  stg<T, EXv[Q] == 0, HSR>(a, w, r);
 }
 
 // Interior fast path of the odd step: every neighbour is inside the grid.
@@ -230,7 +204,8 @@ __device__ __forceinline__ void store_interior_odd(const KParams<T, S>& p, const
   }
 }
 
-// Pre-collision populations of node (i, j) for a state of the given parity.
+// Pre-collision populations of node (i, j) for a state of the given parity,
+// before the odd step's thermal wall conditions (pull_walls).
 template <typename T, bool ODD, typename S>
 __device__ __forceinline__ void load_node_raw(const KParams<T, S>& p, int i, int j, T df[9], T dg[5]) {
   const int64_t o = pop_off(p, i, j);
@@ -241,8 +216,9 @@ __device__ __forceinline__ void load_node_raw(const KParams<T, S>& p, int i, int
     for (int q = 0; q < 5; ++q) dg[q] = ldg<T, true>(p.g + q * p.qs + o);
     return;
   }
-  // The pulls of pull_f / pull_g without the thermal wall conditions (see
-  // pull_walls).  The source column (i - 1, i or i + 1, wrapped on a
+  // Odd step: the pull of direction q into (i, j) reads population OPP[q] of
+  // node (i, j) - e_q, or the node's own population q where that crosses a
+  // wall (bounce-back; the thermal walls' constants are pull_walls').  The source column (i - 1, i or i + 1, wrapped on a
   // periodic axis) and row (j - 1, j or j + 1: wave-uniform) and whether
   // each is inside are worked out once; each address is then a select
   // between two indices, so no branch separates the 14 loads and all of
@@ -280,6 +256,7 @@ __device__ __forceinline__ void pull_walls(const KParams<T, S>& p, int i, T dg[5
   dg[3] = cold ? p.coldc - dg[3] : dg[3];
 }
 
+// Pre-collision populations of node (i, j) for a state of the given parity.
 template <typename T, bool ODD, typename S>
 __device__ __forceinline__ void load_node(const KParams<T, S>& p, int i, int j, T df[9], T dg[5]) {
   load_node_raw<T, ODD>(p, i, j, df, dg);
@@ -311,9 +288,11 @@ __device__ __forceinline__ void store_node(const KParams<T, S>& p, int i, int j,
 #pragma unroll
     for (int q = 0; q < 5; ++q) stg<T, true, HSR>(p.g + OPP[q] * p.qs + o, dg[q], rot_word(r, 9 + q));
   } else {
-    // The pushes of push_f / push_g, with the destination column (i + 1,
-    // i or i - 1, wrapped on a periodic axis), row (wave-uniform) and inside
-    // tests worked out once and each address a select between two indices.
+    // Odd step: post-collision population q goes to slot q of node (i, j) +
+    // e_q, or back into the node's own slot OPP[q] where that crosses a wall;
+    // the destination column (i + 1, i or i - 1, wrapped on a periodic axis),
+    // row (wave-uniform) and inside tests are worked out once and each
+    // address is a select between two indices.
     const int nx = p.nx, ny = p.ny;
     const int ip = p.px && i == nx - 1 ? 0 : i + 1;  // destination column of e_x = +1
     const int im = p.px && i == 0 ? nx - 1 : i - 1;  // of e_x = -1
@@ -333,7 +312,7 @@ __device__ __forceinline__ void store_node(const KParams<T, S>& p, int i, int j,
       const int64_t idx = in ? d * p.qs + rs + di : OPP[d] * p.qs + o;
       T w = q < 9 ? df[d] : dg[d];
       // thermal populations leaving through the hot (x = 0) or cold (x = nx)
-      // wall come back anti-bounced, as in push_g
+      // wall come back anti-bounced: hotc - v or coldc - v
       if (q >= 9 && EXv[d] == -1) w = in ? w : p.hotc - w;
       if (q >= 9 && EXv[d] == 1) w = in ? w : p.coldc - w;
       if (EXv[d] == 0) stg<T, true, HSR>(base + idx, w, rot_word(r, q));
