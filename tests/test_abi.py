@@ -168,6 +168,9 @@ def test_adjoint_workspace_checks():
     for bad in (dict(periodic_x=1), dict(clamp_mode=1), dict(gx=1e-6), dict(dtype="fp16")):
         assert ws(P.make_params(48, 40, **dict(kw, **bad)), 100, 10)[0] == _lib.PM_EINVAL
     assert _lib.lib.pm_last_error(None).decode()
+    # the adjoint's setters reject a missing adjoint before touching anything
+    assert _lib.lib.pm_adjoint_set_lambda_dtype(None, _lib.PM_FP32) == _lib.PM_EINVAL
+    assert _lib.lib.pm_adjoint_set_shear_floor(None, 0.1) == _lib.PM_EINVAL
 
 
 def test_fp16_storage_parameters():

@@ -253,6 +253,13 @@ def test_fp32_adjoint_state_needs_an_fp32_forward():
         P.Adjoint(cav, 10, lambda_dtype="fp32")
     with pytest.raises(ValueError):
         P.Adjoint(P.Cavity(32, dtype="fp32", n=1.0, Ra=1e4, **PHYS), 10, lambda_dtype="fp16")
+    # through the C ABI: only PM_FP64 and PM_FP32 are storage types for it
+    from paper_2011_15073_amd import _lib
+    adj = P.Adjoint(P.Cavity(32, dtype="fp32", n=1.0, Ra=1e4, **PHYS), 10)
+    for code in (_lib.PM_FP16, -1, 7):
+        assert _lib.lib.pm_adjoint_set_lambda_dtype(adj._h, code) == _lib.PM_EINVAL
+    assert _lib.lib.pm_adjoint_set_lambda_dtype(adj._h, _lib.PM_FP32) == 0
+    assert _lib.lib.pm_adjoint_set_lambda_dtype(adj._h, _lib.PM_FP64) == 0
 
 
 def test_256_cavity_n07_exact_adjoint_reports_amplification():
