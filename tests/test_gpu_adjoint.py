@@ -247,6 +247,36 @@ def test_fp32_adjoint_state_tracks_the_fp64_adjoint_state():
     assert dg <= 1e-4
 
 
+@pytest.mark.parametrize("grid", [(24, 24), (70, 19)])
+def test_fp32_adjoint_state_on_ragged_grids(grid):
+    """Partial waves and both parities (T = 60, C = 7): the gradients with
+    the adjoint state stored in FP32 are held against those of the FP64
+    forward, and must not stray further from them than twice the distance
+    the FP32 forward state already puts between the FP64-state gradients
+    and them (the rounding of the stored adjoint state is then no larger
+    than the FP32 forward's own), with a floor of 1e-6 of each gradient's
+    scale."""
+    nx, ny = grid
+    ld = inputs.logda_field(max(nx, ny), seed=3)[:ny, :nx].copy()
+
+    def run(dtype, lam):
+        cav = P.Cavity(nx, ny, dtype=dtype, logda=torch.from_numpy(ld), n=0.7, Ra=1e4, **PHYS)
+        adj = P.Adjoint(cav, 60, 7, lambda_dtype=lam)
+        adj.forward()
+        gld, gn, gRa = adj.backward()
+        adj.close()
+        return gld.cpu().numpy(), gn, gRa
+
+    ref, a64, a32 = run("fp64", "fp64"), run("fp32", "fp64"), run("fp32", "fp32")
+    scale = np.abs(ref[0]).max()
+    e64, e32 = np.abs(a64[0] - ref[0]).max(), np.abs(a32[0] - ref[0]).max()
+    print(f"{grid}: log-Da field {e64:.2e} / {e32:.2e} of {scale:.2e}; dn {ref[1]:.9e} {a64[1]:.9e} {a32[1]:.9e}; "
+          f"dRa {ref[2]:.9e} {a64[2]:.9e} {a32[2]:.9e}", flush=True)
+    assert e32 <= max(2 * e64, 1e-6 * scale)
+    for q in (1, 2):
+        assert abs(a32[q] - ref[q]) <= max(2 * abs(a64[q] - ref[q]), 1e-6 * abs(ref[q]))
+
+
 def test_fp32_adjoint_state_needs_an_fp32_forward():
     cav = P.Cavity(32, dtype="fp64", n=1.0, Ra=1e4, **PHYS)
     with pytest.raises(P.PmError, match="FP32 forward"):
